@@ -1,0 +1,240 @@
+/*
+ * vccl -- virtual-rank collective communication on one AMD MI355X (gfx950).
+ *
+ * R virtual ranks (2..16) live on one GPU.  Every rank owns its own send and
+ * receive buffers (device memory supplied by the caller) and its own FIFO
+ * regions (device memory owned by the library).  A collective is split into
+ * channels; each channel runs as one workgroup per rank, and the workgroups
+ * of a channel hand data to each other through bounded FIFOs of slots,
+ * synchronised by counters (Simple protocol) or by flags embedded in every
+ * line (LL: 4 B data + 4 B flag; LL128: 120 B data + 8 B flag).
+ *
+ * The API follows the paper's description of NCCL's (Section II-A):
+ * communicators created together for all ranks by one thread
+ * (CommInitAll), Destroy and Abort, the five collectives, and
+ * GroupStart/GroupEnd to fuse several calls into one kernel launch.  The
+ * launch model is "one CPU thread for multiple GPUs" (Section II-B): one host
+ * thread issues every rank's call.
+ *
+ * Conventions shared by every entry point:
+ *  - Buffers: plain device pointers (hipMalloc'ed or torch tensors on the same
+ *    device), aligned to the element size, owned by the caller and alive until
+ *    the stream has completed the call.  Counts are elements of the data type.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  When ranks pass different streams, the library joins them with
+ *    events so the single launch follows all of them and all of them follow it.
+ *  - Matching: a collective is issued once all R ranks of the communicator set
+ *    have called it (same call number per rank).  Arguments that must agree
+ *    across ranks (count, type, op, root) are checked at that point; a
+ *    mismatch returns vcclInvalidUsage to the call that completes the set.
+ *  - Errors: argument errors are returned synchronously and nothing is
+ *    enqueued.  Errors that happen on the device (a wait that exceeded the
+ *    timeout, an abort) are reported by vcclCommGetAsyncError; after such an
+ *    error the communicator set must be destroyed.
+ *  - Threads: the API is not thread-safe; drive one communicator set from one
+ *    host thread (Section II-B, "one CPU thread for multiple GPUs").
+ */
+#ifndef VCCL_H
+#define VCCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VCCL_MAJOR 0
+#define VCCL_MINOR 1
+#define VCCL_MAX_RANKS 16
+#define VCCL_MAX_CHANNELS 32
+
+typedef struct vcclComm* vcclComm_t;
+
+typedef enum {
+  vcclSuccess = 0,
+  vcclUnhandledHipError = 1,
+  vcclSystemError = 2,
+  vcclInternalError = 3,
+  vcclInvalidArgument = 4,
+  vcclInvalidUsage = 5,
+  vcclRemoteError = 6, /* a peer did not answer within the timeout, or abort */
+  vcclInProgress = 7
+} vcclResult_t;
+
+typedef enum { vcclInt32 = 0, vcclFloat32 = 1, vcclBfloat16 = 2 } vcclDataType_t;
+typedef enum { vcclSum = 0, vcclMax = 1 } vcclRedOp_t;
+
+/* Algorithms and protocols (Section V-A support table: Tree only for AllReduce). */
+typedef enum { vcclAlgoAuto = -1, vcclAlgoRing = 0, vcclAlgoTree = 1 } vcclAlgo_t;
+typedef enum { vcclProtoAuto = -1, vcclProtoSimple = 0, vcclProtoLL = 1, vcclProtoLL128 = 2 } vcclProto_t;
+
+const char* vcclGetErrorString(vcclResult_t result);
+vcclResult_t vcclGetVersion(int* version); /* major*100 + minor */
+
+/* ---------------------------------------------------------------- communicators */
+
+/* Section II-A, "Communicator Management": ncclCommInitAll creates all
+ * communicators of a single process/thread at once.  Creates `nranks`
+ * (2..16) virtual-rank communicators on one device: devlist == NULL uses the
+ * current HIP device, otherwise devlist[0] names it and every other entry
+ * must name the same device.  Allocates the FIFOs and counters of every
+ * (channel, rank, connection) and builds the ring and the double binary tree
+ * (Section II-C).  comms[] (caller-owned array of nranks handles) receives one
+ * handle per rank.  Errors: vcclInvalidArgument for a bad count or device,
+ * vcclUnhandledHipError if device memory cannot be obtained. */
+vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist);
+
+/* Section II-A: ncclCommDestroy completes pending operations, then frees.
+ * Destroying any rank's handle waits for all work of the set and frees the
+ * set's resources once every rank's handle has been destroyed. */
+vcclResult_t vcclCommDestroy(vcclComm_t comm);
+
+/* Section II-A: ncclCommAbort terminates at once and cancels ongoing
+ * operations.  Sets the set's abort word (host memory the device polls in every
+ * wait loop); running kernels leave their waits and exit; pending unmatched
+ * calls are dropped.  The handles stay valid only for Destroy. */
+vcclResult_t vcclCommAbort(vcclComm_t comm);
+
+/* vcclSuccess, or the first device-side error of the set (vcclRemoteError
+ * after a timeout or an abort).  Does not synchronise. */
+vcclResult_t vcclCommGetAsyncError(vcclComm_t comm, vcclResult_t* asyncError);
+
+vcclResult_t vcclCommCount(vcclComm_t comm, int* count);
+vcclResult_t vcclCommUserRank(vcclComm_t comm, int* rank);
+
+/* ---------------------------------------------------------------- collectives
+ * Section II-A, "Collective Communication": the five collectives.  Step
+ * sequences: Section V-E.  Every call below is made once per rank with that
+ * rank's comm handle and buffers. */
+
+/* recv[i] = op over ranks of send[i], i < count, on every rank.  In place
+ * when send == recv.  Ring (Section V-E, Ring AllReduce) or double binary
+ * tree (Section V-E, Tree AllReduce). */
+vcclResult_t vcclAllReduce(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype,
+                           vcclRedOp_t op, vcclComm_t comm, void* stream);
+
+/* recv = send of `root` on every rank (a chain from the root along the ring,
+ * Section V-E, Ring Broadcast).  sendbuff is read on the root only (other
+ * ranks may pass NULL); in place when the root's send == recv. */
+vcclResult_t vcclBroadcast(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype, int root,
+                           vcclComm_t comm, void* stream);
+
+/* recv (root only) = op over ranks of send (a chain ending at the root,
+ * Section V-E, Ring Reduce).  Non-root recvbuff is neither read nor written
+ * (may be NULL). */
+vcclResult_t vcclReduce(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype,
+                        vcclRedOp_t op, int root, vcclComm_t comm, void* stream);
+
+/* recv[q*sendcount + i] = send of rank q [i] (Section V-E, Ring AllGather).
+ * recvbuff holds nranks*sendcount elements.  In place when
+ * send == recv + rank*sendcount. */
+vcclResult_t vcclAllGather(const void* sendbuff, void* recvbuff, size_t sendcount, vcclDataType_t datatype,
+                           vcclComm_t comm, void* stream);
+
+/* recv[i] = op over ranks of send[rank*recvcount + i] (Section V-E, Ring
+ * ReduceScatter).  sendbuff holds nranks*recvcount elements.  In place when
+ * recv == send + rank*recvcount. */
+vcclResult_t vcclReduceScatter(const void* sendbuff, void* recvbuff, size_t recvcount, vcclDataType_t datatype,
+                               vcclRedOp_t op, vcclComm_t comm, void* stream);
+
+/* Section II-A, "Group Calls": calls between GroupStart and GroupEnd are
+ * deferred and executed together as part of one launch.  Groups nest; the
+ * outermost GroupEnd plans every collective matched inside the group (per
+ * communicator set: one persistent kernel over a work list, each collective
+ * split into channels placed on lanes) and launches it.  A group that ends
+ * with unmatched calls returns vcclInvalidUsage and issues nothing. */
+vcclResult_t vcclGroupStart(void);
+vcclResult_t vcclGroupEnd(void);
+
+/* ---------------------------------------------------------------- tuning
+ * Section III-D and Section II-C: the algorithm and protocol are chosen per
+ * call (user setting, else a tuning model), then the channel count.  The
+ * library's tuner does the same; these calls and the environment variables
+ * VCCL_ALGO, VCCL_PROTO (simple|ll|ll128), VCCL_NCHANNELS, VCCL_CHUNK_BYTES,
+ * VCCL_NTHREADS, VCCL_DIRECT override it for the whole communicator set.
+ * A negative / zero field means "tuner decides". */
+typedef struct {
+  int algo;           /* vcclAlgo_t */
+  int proto;          /* vcclProto_t */
+  int nchannels;      /* 1..VCCL_MAX_CHANNELS */
+  int nthreads;       /* workgroup size: 64..1024, multiple of 64 */
+  size_t chunkBytes;  /* elementary-step chunk, multiple of 16, <= slot payload */
+  int direct;         /* 1: P2P_DIRECT-style copies into peer buffers (Simple only) */
+} vcclTuning_t;
+
+vcclResult_t vcclCommSetTuning(vcclComm_t comm, const vcclTuning_t* tuning);
+
+/* What the most recent launch of the set used (for tests and benchmarks). */
+typedef struct {
+  int algo, proto, nchannels, nthreads, direct, nlanes, nitems, ncolls;
+  size_t chunkBytes;
+  int grid;           /* workgroups launched */
+} vcclPlanInfo_t;
+vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info);
+
+/* Device-side completion time (ns, device wall clock) of each collective of
+ * the most recent launch, in issue order; waits for that launch.  n is the
+ * capacity of stamps_ns (host array); *written receives the count. */
+vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int n, int* written);
+
+/* ---------------------------------------------------------------- failure handling
+ * Every wait on the device is bounded: after `timeout_us` microseconds without
+ * progress the waiting workgroup records vcclRemoteError and exits. */
+vcclResult_t vcclCommSetTimeout(vcclComm_t comm, uint64_t timeout_us);
+
+/* Test hook: the workgroups of every rank whose bit is set in `mask` skip all
+ * their work, so their peers must time out (see vcclCommSetTimeout). */
+vcclResult_t vcclCommDebugSetDeadRanks(vcclComm_t comm, uint32_t mask);
+
+/* Copies `bytes` bytes of the FIFO of connection (channel, receiving rank,
+ * connection 0 = ring) for protocol `proto` starting at byte `offset` into the
+ * host buffer `dst`.  Synchronises the device.  For line-format checks. */
+vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int proto, size_t offset, void* dst,
+                                   size_t bytes);
+
+/* ---------------------------------------------------------------- probes
+ * Section III-C: LL128 depends on 128-byte stores that are never split or
+ * reordered; NCCL disables it where that is not guaranteed.  The tear test
+ * runs `pairs` writer/reader workgroup pairs that exchange `lines` lines per
+ * round for `rounds` rounds, every payload word derived from (flag, index);
+ * *torn receives the number of lines whose flag was current but whose
+ * payload was not.  Synchronises the device. */
+vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, uint64_t* torn, uint64_t* checked);
+
+/* XCC (accelerator die) id of each of `n` workgroups of a plain launch,
+ * written to the host array ids[n].  Synchronises the device. */
+vcclResult_t vcclProbeXccIds(int n, int* ids);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching over one persistent kernel: requests are admitted
+ * while earlier ones still run, as lanes and the staging budget free up. */
+typedef struct vcclServer* vcclServer_t;
+
+typedef struct {
+  int coll;                        /* 0 AllReduce, 1 Broadcast, 2 Reduce, 3 AllGather, 4 ReduceScatter */
+  int datatype;                    /* vcclDataType_t */
+  int op;                          /* vcclRedOp_t */
+  int root;
+  size_t count;                    /* as the per-call API's count / sendcount / recvcount */
+  const void* send[VCCL_MAX_RANKS];/* per-rank device buffers, caller-owned */
+  void* recv[VCCL_MAX_RANKS];
+} vcclRequest_t;
+
+/* budgetBytes: device bytes the in-flight requests may hold (their send and
+ * receive buffers plus the FIFOs of the lanes they occupy); lanes: concurrent
+ * lanes of the persistent kernel (each lane = one workgroup per rank). */
+vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, vcclServer_t* server);
+/* Non-blocking: queues the request; *id receives its identifier. */
+vcclResult_t vcclServeSubmit(vcclServer_t server, const vcclRequest_t* req, uint64_t* id);
+/* Makes progress (admits queued requests, retires finished ones) and
+ * reports whether `id` has completed; t_done_ns receives the host
+ * monotonic time (ns) at which completion was observed. */
+vcclResult_t vcclServeTest(vcclServer_t server, uint64_t id, int* done, vcclResult_t* status, uint64_t* t_done_ns);
+/* Drains every request, stops the persistent kernel and frees. */
+vcclResult_t vcclServeDestroy(vcclServer_t server);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCCL_H */

@@ -1,0 +1,302 @@
+"""Python binding of the vccl C ABI (include/vccl.h): argument marshalling only.
+
+Every function keeps the C name and argument order.  Buffers may be given as
+torch tensors (their ``data_ptr()`` is passed), integers (device addresses)
+or None (NULL); streams as ``torch.cuda.Stream``, an integer hipStream_t or
+None (the null stream).  A result other than vcclSuccess raises VcclError
+carrying the code; functions that return values through pointers in C return
+them here.
+
+The native library is paper_2507_04786_amd/lib/libvccl.so, built in-tree by
+``paper_2507_04786_amd.build.build()``.  Importing this module without it
+raises ImportError: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libvccl.so")
+
+# ---------------------------------------------------------------- constants (vccl.h)
+vcclSuccess = 0
+vcclUnhandledHipError = 1
+vcclSystemError = 2
+vcclInternalError = 3
+vcclInvalidArgument = 4
+vcclInvalidUsage = 5
+vcclRemoteError = 6
+vcclInProgress = 7
+
+vcclInt32, vcclFloat32, vcclBfloat16 = 0, 1, 2
+vcclSum, vcclMax = 0, 1
+vcclAlgoAuto, vcclAlgoRing, vcclAlgoTree = -1, 0, 1
+vcclProtoAuto, vcclProtoSimple, vcclProtoLL, vcclProtoLL128 = -1, 0, 1, 2
+VCCL_MAX_RANKS = 16
+VCCL_MAX_CHANNELS = 32
+
+COLL_ALLREDUCE, COLL_BROADCAST, COLL_REDUCE, COLL_ALLGATHER, COLL_REDUCESCATTER = 0, 1, 2, 3, 4
+
+DTYPE_NAMES = {"int32": vcclInt32, "float32": vcclFloat32, "bfloat16": vcclBfloat16}
+PROTO_NAMES = {"simple": vcclProtoSimple, "ll": vcclProtoLL, "ll128": vcclProtoLL128}
+ALGO_NAMES = {"ring": vcclAlgoRing, "tree": vcclAlgoTree}
+OP_NAMES = {"sum": vcclSum, "max": vcclMax}
+
+
+class VcclError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {vcclGetErrorString(code)} ({code})")
+
+
+class vcclTuning_t(C.Structure):
+    _fields_ = [("algo", C.c_int), ("proto", C.c_int), ("nchannels", C.c_int), ("nthreads", C.c_int),
+                ("chunkBytes", C.c_size_t), ("direct", C.c_int)]
+
+
+class vcclPlanInfo_t(C.Structure):
+    _fields_ = [("algo", C.c_int), ("proto", C.c_int), ("nchannels", C.c_int), ("nthreads", C.c_int),
+                ("direct", C.c_int), ("nlanes", C.c_int), ("nitems", C.c_int), ("ncolls", C.c_int),
+                ("chunkBytes", C.c_size_t), ("grid", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class vcclRequest_t(C.Structure):
+    _fields_ = [("coll", C.c_int), ("datatype", C.c_int), ("op", C.c_int), ("root", C.c_int),
+                ("count", C.c_size_t), ("send", C.c_void_p * VCCL_MAX_RANKS), ("recv", C.c_void_p * VCCL_MAX_RANKS)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"vccl native library not built: {LIB_PATH} is missing "
+                          "(run paper_2507_04786_amd.build.build())")
+    lib = C.CDLL(LIB_PATH)
+    P, I, U64, SZ, VP = C.c_void_p, C.c_int, C.c_uint64, C.c_size_t, C.c_void_p
+    sig = {
+        "vcclGetErrorString": (C.c_char_p, [I]),
+        "vcclGetVersion": (I, [C.POINTER(I)]),
+        "vcclCommInitAll": (I, [C.POINTER(P), I, C.POINTER(I)]),
+        "vcclCommDestroy": (I, [P]),
+        "vcclCommAbort": (I, [P]),
+        "vcclCommGetAsyncError": (I, [P, C.POINTER(I)]),
+        "vcclCommCount": (I, [P, C.POINTER(I)]),
+        "vcclCommUserRank": (I, [P, C.POINTER(I)]),
+        "vcclAllReduce": (I, [VP, VP, SZ, I, I, P, VP]),
+        "vcclBroadcast": (I, [VP, VP, SZ, I, I, P, VP]),
+        "vcclReduce": (I, [VP, VP, SZ, I, I, I, P, VP]),
+        "vcclAllGather": (I, [VP, VP, SZ, I, P, VP]),
+        "vcclReduceScatter": (I, [VP, VP, SZ, I, I, P, VP]),
+        "vcclGroupStart": (I, []),
+        "vcclGroupEnd": (I, []),
+        "vcclCommSetTuning": (I, [P, C.POINTER(vcclTuning_t)]),
+        "vcclCommGetLastPlan": (I, [P, C.POINTER(vcclPlanInfo_t)]),
+        "vcclCommGetLastTimestamps": (I, [P, C.POINTER(U64), I, C.POINTER(I)]),
+        "vcclCommSetTimeout": (I, [P, U64]),
+        "vcclCommDebugSetDeadRanks": (I, [P, C.c_uint32]),
+        "vcclCommDebugReadFifo": (I, [P, I, I, I, SZ, VP, SZ]),
+        "vcclProbeLL128Tear": (I, [I, I, I, C.POINTER(U64), C.POINTER(U64)]),
+        "vcclProbeXccIds": (I, [I, C.POINTER(I)]),
+        "vcclServeCreate": (I, [C.POINTER(P), SZ, I, C.POINTER(P)]),
+        "vcclServeSubmit": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64)]),
+        "vcclServeTest": (I, [P, U64, C.POINTER(I), C.POINTER(I), C.POINTER(U64)]),
+        "vcclServeDestroy": (I, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy vcclCommAbort "
+            "vcclCommGetAsyncError vcclCommCount vcclCommUserRank vcclAllReduce vcclBroadcast vcclReduce "
+            "vcclAllGather vcclReduceScatter vcclGroupStart vcclGroupEnd vcclCommSetTuning vcclCommGetLastPlan "
+            "vcclCommGetLastTimestamps vcclCommSetTimeout vcclCommDebugSetDeadRanks vcclCommDebugReadFifo "
+            "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
+            "vcclServeDestroy").split()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    return int(x)
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return s.cuda_stream
+    return int(s)
+
+
+def _check(res, where):
+    if res != vcclSuccess:
+        raise VcclError(res, where)
+
+
+def vcclGetErrorString(code: int) -> str:
+    return _lib.vcclGetErrorString(int(code)).decode()
+
+
+def vcclGetVersion() -> int:
+    v = C.c_int()
+    _check(_lib.vcclGetVersion(C.byref(v)), "vcclGetVersion")
+    return v.value
+
+
+def vcclCommInitAll(nranks: int, devlist=None) -> list:
+    arr = (C.c_void_p * nranks)()
+    dl = None if devlist is None else (C.c_int * nranks)(*devlist)
+    _check(_lib.vcclCommInitAll(arr, int(nranks), dl), "vcclCommInitAll")
+    return [C.c_void_p(arr[i]) for i in range(nranks)]
+
+
+def vcclCommDestroy(comm):
+    _check(_lib.vcclCommDestroy(comm), "vcclCommDestroy")
+
+
+def vcclCommAbort(comm):
+    _check(_lib.vcclCommAbort(comm), "vcclCommAbort")
+
+
+def vcclCommGetAsyncError(comm) -> int:
+    v = C.c_int()
+    _check(_lib.vcclCommGetAsyncError(comm, C.byref(v)), "vcclCommGetAsyncError")
+    return v.value
+
+
+def vcclCommCount(comm) -> int:
+    v = C.c_int()
+    _check(_lib.vcclCommCount(comm, C.byref(v)), "vcclCommCount")
+    return v.value
+
+
+def vcclCommUserRank(comm) -> int:
+    v = C.c_int()
+    _check(_lib.vcclCommUserRank(comm, C.byref(v)), "vcclCommUserRank")
+    return v.value
+
+
+def vcclAllReduce(send, recv, count, datatype, op, comm, stream=None):
+    _check(_lib.vcclAllReduce(_ptr(send), _ptr(recv), int(count), int(datatype), int(op), comm, _stream(stream)),
+           "vcclAllReduce")
+
+
+def vcclBroadcast(send, recv, count, datatype, root, comm, stream=None):
+    _check(_lib.vcclBroadcast(_ptr(send), _ptr(recv), int(count), int(datatype), int(root), comm, _stream(stream)),
+           "vcclBroadcast")
+
+
+def vcclReduce(send, recv, count, datatype, op, root, comm, stream=None):
+    _check(_lib.vcclReduce(_ptr(send), _ptr(recv), int(count), int(datatype), int(op), int(root), comm,
+                           _stream(stream)), "vcclReduce")
+
+
+def vcclAllGather(send, recv, sendcount, datatype, comm, stream=None):
+    _check(_lib.vcclAllGather(_ptr(send), _ptr(recv), int(sendcount), int(datatype), comm, _stream(stream)),
+           "vcclAllGather")
+
+
+def vcclReduceScatter(send, recv, recvcount, datatype, op, comm, stream=None):
+    _check(_lib.vcclReduceScatter(_ptr(send), _ptr(recv), int(recvcount), int(datatype), int(op), comm,
+                                  _stream(stream)), "vcclReduceScatter")
+
+
+def vcclGroupStart():
+    _check(_lib.vcclGroupStart(), "vcclGroupStart")
+
+
+def vcclGroupEnd():
+    _check(_lib.vcclGroupEnd(), "vcclGroupEnd")
+
+
+def vcclCommSetTuning(comm, algo=-1, proto=-1, nchannels=0, nthreads=0, chunkBytes=0, direct=-1):
+    t = vcclTuning_t(int(algo), int(proto), int(nchannels), int(nthreads), int(chunkBytes), int(direct))
+    _check(_lib.vcclCommSetTuning(comm, C.byref(t)), "vcclCommSetTuning")
+
+
+def vcclCommGetLastPlan(comm) -> dict:
+    info = vcclPlanInfo_t()
+    _check(_lib.vcclCommGetLastPlan(comm, C.byref(info)), "vcclCommGetLastPlan")
+    return info.as_dict()
+
+
+def vcclCommGetLastTimestamps(comm, n: int) -> list:
+    arr = (C.c_uint64 * n)()
+    w = C.c_int()
+    _check(_lib.vcclCommGetLastTimestamps(comm, arr, int(n), C.byref(w)), "vcclCommGetLastTimestamps")
+    return [arr[i] for i in range(w.value)]
+
+
+def vcclCommSetTimeout(comm, timeout_us: int):
+    _check(_lib.vcclCommSetTimeout(comm, int(timeout_us)), "vcclCommSetTimeout")
+
+
+def vcclCommDebugSetDeadRanks(comm, mask: int):
+    _check(_lib.vcclCommDebugSetDeadRanks(comm, int(mask)), "vcclCommDebugSetDeadRanks")
+
+
+def vcclCommDebugReadFifo(comm, channel, rank, proto, offset, nbytes) -> bytes:
+    buf = (C.c_uint8 * int(nbytes))()
+    _check(_lib.vcclCommDebugReadFifo(comm, int(channel), int(rank), int(proto), int(offset), buf, int(nbytes)),
+           "vcclCommDebugReadFifo")
+    return bytes(buf)
+
+
+def vcclProbeLL128Tear(pairs: int, lines: int, rounds: int):
+    torn, checked = C.c_uint64(), C.c_uint64()
+    res = _lib.vcclProbeLL128Tear(int(pairs), int(lines), int(rounds), C.byref(torn), C.byref(checked))
+    if res not in (vcclSuccess, vcclRemoteError):
+        raise VcclError(res, "vcclProbeLL128Tear")
+    return torn.value, checked.value, res
+
+
+def vcclProbeXccIds(n: int) -> list:
+    arr = (C.c_int * n)()
+    _check(_lib.vcclProbeXccIds(int(n), arr), "vcclProbeXccIds")
+    return list(arr)
+
+
+def vcclServeCreate(comms, budgetBytes: int, lanes: int):
+    arr = (C.c_void_p * len(comms))(*[c.value for c in comms])
+    out = C.c_void_p()
+    _check(_lib.vcclServeCreate(arr, int(budgetBytes), int(lanes), C.byref(out)), "vcclServeCreate")
+    return out
+
+
+def vcclServeSubmit(server, coll, datatype, op, root, count, sends, recvs) -> int:
+    req = vcclRequest_t()
+    req.coll, req.datatype, req.op, req.root, req.count = int(coll), int(datatype), int(op), int(root), int(count)
+    for i, s in enumerate(sends):
+        req.send[i] = _ptr(s)
+    for i, r in enumerate(recvs):
+        req.recv[i] = _ptr(r)
+    rid = C.c_uint64()
+    _check(_lib.vcclServeSubmit(server, C.byref(req), C.byref(rid)), "vcclServeSubmit")
+    return rid.value
+
+
+def vcclServeTest(server, rid: int):
+    done, status, t = C.c_int(), C.c_int(), C.c_uint64()
+    _check(_lib.vcclServeTest(server, int(rid), C.byref(done), C.byref(status), C.byref(t)), "vcclServeTest")
+    return bool(done.value), status.value, t.value
+
+
+def vcclServeDestroy(server):
+    _check(_lib.vcclServeDestroy(server), "vcclServeDestroy")
+
+
+def torch_dtype_code(dt) -> int:
+    import torch
+    return {torch.int32: vcclInt32, torch.float32: vcclFloat32, torch.bfloat16: vcclBfloat16}[dt]

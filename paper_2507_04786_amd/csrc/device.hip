@@ -1,0 +1,1098 @@
+// gfx950 kernels of the virtual-rank collectives.
+//
+// One workgroup runs one (lane, rank): it executes, for every work item of its
+// lane, that rank's primitive sequence (Section V-E step tables) on the item's
+// channel region.  Workgroups of the same lane exchange data through FIFOs in
+// HBM under one of three protocols (Section III):
+//
+//  * Simple: a slot holds a whole chunk.  The sender waits for a free slot
+//    (head counter), stores the chunk, makes it visible at device scope
+//    (every wave drains its stores, then one release fence) and publishes the
+//    tail counter; the receiver waits on tail, acquires, reads the slot and
+//    returns the slot through head.  The receiver waits for the full chunk.
+//  * LL: every 8-byte unit carries 4 bytes of data and a 4-byte flag and is
+//    written and read by one 64-bit device-scope atomic access, so no fence
+//    is needed; the receiver polls each unit's flag.
+//  * LL128: every 128-byte line carries 120 bytes of data and an 8-byte flag
+//    and is written by one 16-byte store per lane across 8 lanes (one store
+//    instruction) and read back the same way; the receiver checks the flag
+//    word and re-reads the whole line until it is current.  This relies on
+//    128-byte lines not being torn (see the tear probe below).
+//
+// Section V-D's mapping is kept where it holds on CDNA: a channel is a
+// workgroup per rank, wave 0 stages the work descriptor in LDS, all waves of
+// the workgroup move 16-byte vectors in an unrolled, wave-uniform loop.
+// "Direct" variants (Section IV-A, P2P_DIRECT) write straight into the peer's
+// receive buffer instead of its FIFO while keeping the head/tail protocol.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vccl_dev.h"
+
+namespace vccl {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ memory access
+
+__device__ __forceinline__ uint64_t ldAgent(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stAgent(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ldSystem32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void orSystem32(uint32_t* p, uint32_t v) {
+  __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// Drain this wave's outstanding vector memory operations (vmcnt(0)).  A bare
+// workgroup barrier does not wait for them on gfx950.
+__device__ __forceinline__ void drainVmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+__device__ __forceinline__ uint64_t nowTicks() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t makeRsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+// 16-byte load / store with device-scope coherence (sc1): bypasses the
+// non-coherent per-CU cache so a line written by another workgroup is seen.
+__device__ __forceinline__ u32x4 ldLine16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 16);
+}
+__device__ __forceinline__ void stLine16(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 16);
+}
+
+// ------------------------------------------------------------------ element operators
+// Words are 32-bit and hold one int32 / fp32 element or two bf16 elements.
+
+__device__ __forceinline__ uint32_t bf16Round(float s) {
+  // round to nearest even (inputs are NaN-free)
+  uint32_t u = __float_as_uint(s);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float fmaxRule(float a, float b) {
+  // a > b ? a : (b > a ? b : (signbit(a) ? b : a)) -- max preferring +0
+  return a > b ? a : (b > a ? b : (__float_as_uint(a) >> 31 ? b : a));
+}
+
+template <int DT, int OP>
+__device__ __forceinline__ uint32_t redWord(uint32_t a, uint32_t b) {
+  if constexpr (DT == DT_I32) {
+    if constexpr (OP == OP_SUM) return a + b;
+    else return (int32_t)a > (int32_t)b ? a : b;
+  } else if constexpr (DT == DT_F32) {
+    float fa = __uint_as_float(a), fb = __uint_as_float(b);
+    if constexpr (OP == OP_SUM) return __float_as_uint(fa + fb);
+    else return __float_as_uint(fmaxRule(fa, fb));
+  } else if constexpr (DT == DT_BF16) {
+    float al = __uint_as_float(a << 16), bl = __uint_as_float(b << 16);
+    float ah = __uint_as_float(a & 0xFFFF0000u), bh = __uint_as_float(b & 0xFFFF0000u);
+    if constexpr (OP == OP_SUM) {
+      return bf16Round(al + bl) | (bf16Round(ah + bh) << 16);
+    } else {
+      // the result is one of the inputs: pick it by the max rule on the widened values
+      const bool pickLo = bl > al || (!(al > bl) && !(bl > al) && (__float_as_uint(al) >> 31));
+      const bool pickHi = bh > ah || (!(ah > bh) && !(bh > ah) && (__float_as_uint(ah) >> 31));
+      return (pickLo ? (b & 0xFFFFu) : (a & 0xFFFFu)) | (pickHi ? (b & 0xFFFF0000u) : (a & 0xFFFF0000u));
+    }
+  } else {
+    return b;
+  }
+}
+
+template <int DT, int OP>
+__device__ __forceinline__ uint4 redVec(uint4 a, uint4 b) {
+  return make_uint4(redWord<DT, OP>(a.x, b.x), redWord<DT, OP>(a.y, b.y), redWord<DT, OP>(a.z, b.z),
+                    redWord<DT, OP>(a.w, b.w));
+}
+
+template <int DT, int OP>
+__device__ __forceinline__ u32x4 redVec4(u32x4 a, u32x4 b) {
+  return u32x4{redWord<DT, OP>(a.x, b.x), redWord<DT, OP>(a.y, b.y), redWord<DT, OP>(a.z, b.z),
+               redWord<DT, OP>(a.w, b.w)};
+}
+
+template <int DT> struct ElemSize { static constexpr int value = (DT == DT_BF16) ? 2 : (DT == DT_U8 ? 1 : 4); };
+
+// Partial (or misaligned) payload access: element by element, never touching
+// bytes at or beyond `valid`.  Pointers are element-aligned.
+template <int E, int NW>
+__device__ __forceinline__ void loadPart(const char* p, int valid, uint32_t (&w)[NW]) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) w[k] = 0;
+#pragma unroll
+  for (int i = 0; i < NW * 4 / E; ++i) {
+    if (i * E < valid) {
+      uint32_t v;
+      if constexpr (E == 4) v = *(const uint32_t*)(p + i * 4);
+      else if constexpr (E == 2) v = *(const uint16_t*)(p + i * 2);
+      else v = *(const uint8_t*)(p + i);
+      w[(i * E) / 4] |= v << (8 * ((i * E) % 4));
+    }
+  }
+}
+template <int E, int NW>
+__device__ __forceinline__ void storePart(char* p, int valid, const uint32_t (&w)[NW]) {
+#pragma unroll
+  for (int i = 0; i < NW * 4 / E; ++i) {
+    if (i * E < valid) {
+      uint32_t v = w[(i * E) / 4] >> (8 * ((i * E) % 4));
+      if constexpr (E == 4) *(uint32_t*)(p + i * 4) = v;
+      else if constexpr (E == 2) *(uint16_t*)(p + i * 2) = (uint16_t)v;
+      else *(uint8_t*)(p + i) = (uint8_t)v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ context
+
+struct Ctx {
+  const DevComm* comm;
+  int rank, lane, nranks;
+  int tid, nthreads, wave, nwaves, lid;
+  int* sAbort;  // LDS flag: set when any wait of this workgroup failed
+};
+
+struct Conn {
+  char* fifo = nullptr;       // this connection's FIFO for the current protocol
+  uint64_t* tail = nullptr;
+  uint64_t* head = nullptr;
+  uint64_t step = 0;
+};
+
+// Slot (step % NSLOTS) may be overwritten once the receiver has consumed step
+// step - NSLOTS, i.e. once head >= step + 1 - NSLOTS.
+__device__ __forceinline__ uint64_t creditTarget(uint64_t step) { return step + 1 > NSLOTS ? step + 1 - NSLOTS : 0; }
+
+// Bounded wait for *ctr >= target, one lane.  Returns false (and records the
+// error) on timeout or abort.
+__device__ __noinline__ bool waitCounter(const Ctx& c, const uint64_t* ctr, uint64_t target) {
+  if (ldAgent(ctr) >= target) return true;
+  uint64_t t0 = nowTicks();
+  uint32_t it = 0;
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (ldAgent(ctr) >= target) return true;
+    if ((++it & 63u) == 0) {
+      if (ldSystem32(c.comm->abortFlag)) { orSystem32(c.comm->errorWord, ERR_ABORT); return false; }
+      if (nowTicks() - t0 > c.comm->timeoutTicks) { orSystem32(c.comm->errorWord, ERR_TIMEOUT); return false; }
+    }
+  }
+}
+
+// Per-lane poll helper for flag-based protocols: counts spins and checks the
+// abort word / timeout now and then.
+struct Spinner {
+  uint64_t t0 = 0;
+  uint32_t it = 0;
+  __device__ __forceinline__ bool tick(const Ctx& c) {
+    if ((++it & 255u) == 0) {
+      if (*(volatile int*)c.sAbort) return false;
+      if (t0 == 0) t0 = nowTicks();
+      if (ldSystem32(c.comm->abortFlag)) { orSystem32(c.comm->errorWord, ERR_ABORT); atomicOr(c.sAbort, 1); return false; }
+      if (nowTicks() - t0 > c.comm->timeoutTicks) {
+        orSystem32(c.comm->errorWord, ERR_TIMEOUT);
+        atomicOr(c.sAbort, 1);
+        return false;
+      }
+    }
+    return true;
+  }
+};
+
+// ------------------------------------------------------------------ Simple datapath
+
+// Up to three pointers filled in order; every access uses a constant index so
+// the list stays in registers.
+struct PtrList {
+  const char* p0 = nullptr;
+  const char* p1 = nullptr;
+  const char* p2 = nullptr;
+  int n = 0;
+  __device__ __forceinline__ void add(const char* v) {
+    if (n == 0) p0 = v;
+    else if (n == 1) p1 = v;
+    else p2 = v;
+    ++n;
+  }
+  __device__ __forceinline__ const char* get(int k) const { return k == 0 ? p0 : (k == 1 ? p1 : p2); }
+};
+
+// out[o] = in[0] (+) in[1] (+) in[2] over 16-byte vectors; every pointer 16-aligned.
+// Buffer instructions: one lane offset register shared by every stream, the
+// unroll stride in a scalar offset, and hardware range checks (an access past
+// the stream's end reads zero and writes nothing), so the loop needs no
+// per-vector bounds test.
+template <int DT, int OP, int NIN, int NOUT>
+__device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, const PtrList& out, uint32_t nvec) {
+  constexpr int U = 4;
+  const uint32_t nb = nvec * 16;
+  const uint32_t stride = (uint32_t)c.nthreads * 16;
+  const __amdgpu_buffer_rsrc_t i0 = makeRsrc(in.p0, nb);
+  const __amdgpu_buffer_rsrc_t i1 = makeRsrc(in.p1, nb);
+  const __amdgpu_buffer_rsrc_t i2 = makeRsrc(in.p2, nb);
+  const __amdgpu_buffer_rsrc_t o0 = makeRsrc(out.p0, nb);
+  const __amdgpu_buffer_rsrc_t o1 = makeRsrc(out.p1, nb);
+  const __amdgpu_buffer_rsrc_t o2 = makeRsrc(out.p2, nb);
+  for (uint32_t base = (uint32_t)c.tid * 16; base < nb; base += stride * U) {
+    u32x4 v0[U], v1[U], v2[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v0[u] = __builtin_amdgcn_raw_buffer_load_b128(i0, base, u * stride, 0);
+      if constexpr (NIN > 1) v1[u] = __builtin_amdgcn_raw_buffer_load_b128(i1, base, u * stride, 0);
+      if constexpr (NIN > 2) v2[u] = __builtin_amdgcn_raw_buffer_load_b128(i2, base, u * stride, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      u32x4 acc = v0[u];
+      if constexpr (NIN > 1) acc = redVec4<DT, OP>(acc, v1[u]);
+      if constexpr (NIN > 2) acc = redVec4<DT, OP>(acc, v2[u]);
+      __builtin_amdgcn_raw_buffer_store_b128(acc, o0, base, u * stride, 0);
+      if constexpr (NOUT > 1) __builtin_amdgcn_raw_buffer_store_b128(acc, o1, base, u * stride, 0);
+      if constexpr (NOUT > 2) __builtin_amdgcn_raw_buffer_store_b128(acc, o2, base, u * stride, 0);
+    }
+  }
+}
+
+// Same operation on any element-aligned pointers, 16 bytes (or the tail) per
+// lane through element-wise accesses.  Used for misaligned buffers and tails.
+template <int DT, int OP, int NIN, int NOUT>
+__device__ __forceinline__ void reduceCopyPart(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t begin,
+                                               uint64_t nbytes) {
+  constexpr int E = ElemSize<DT>::value;
+  for (uint64_t off = begin + (uint64_t)c.tid * 16; off < nbytes; off += (uint64_t)c.nthreads * 16) {
+    const int valid = (int)((nbytes - off) < 16 ? (nbytes - off) : 16);
+    uint32_t acc[4], w[4];
+    loadPart<E, 4>(in.p0 + off, valid, acc);
+    if constexpr (NIN > 1) {
+      loadPart<E, 4>(in.p1 + off, valid, w);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = redWord<DT, OP>(acc[q], w[q]);
+    }
+    if constexpr (NIN > 2) {
+      loadPart<E, 4>(in.p2 + off, valid, w);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = redWord<DT, OP>(acc[q], w[q]);
+    }
+    storePart<E, 4>((char*)out.p0 + off, valid, acc);
+    if constexpr (NOUT > 1) storePart<E, 4>((char*)out.p1 + off, valid, acc);
+    if constexpr (NOUT > 2) storePart<E, 4>((char*)out.p2 + off, valid, acc);
+  }
+}
+
+template <int DT, int OP, int NIN, int NOUT>
+__device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
+  const uintptr_t bits = (uintptr_t)in.p0 | (uintptr_t)in.p1 | (uintptr_t)in.p2 | (uintptr_t)out.p0 |
+                         (uintptr_t)out.p1 | (uintptr_t)out.p2;
+  if ((bits & 15) == 0) {
+    const uint32_t nvec = (uint32_t)(nbytes / 16);
+    reduceCopyVec<DT, OP, NIN, NOUT>(c, in, out, nvec);
+    if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT>(c, in, out, (uint64_t)nvec * 16, nbytes);
+  } else {
+    reduceCopyPart<DT, OP, NIN, NOUT>(c, in, out, 0, nbytes);
+  }
+}
+
+template <int DT, int OP>
+__device__ void reduceCopyN(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
+  if (nbytes == 0 || in.n == 0 || out.n == 0) return;
+#define VCCL_RC(I, O) \
+  if (in.n == I && out.n == O) { reduceCopy<DT, OP, I, O>(c, in, out, nbytes); return; }
+  VCCL_RC(1, 1) VCCL_RC(1, 2) VCCL_RC(1, 3) VCCL_RC(2, 1) VCCL_RC(2, 2) VCCL_RC(2, 3) VCCL_RC(3, 1) VCCL_RC(3, 2)
+  VCCL_RC(3, 3)
+#undef VCCL_RC
+}
+
+// ------------------------------------------------------------------ one elementary step
+//
+// Receives from the connections in rmask, sends to those in smask.  The data
+// combined is: src (if any) first, then each received slot in connection
+// order; it is stored to dst (if any) and to every send target.
+//  recvDirect: the data of the receive is already in dst (a peer wrote it
+//              there directly); only synchronise, and forward dst's content.
+//  sendDirect[j]: non-null -> send j stores into that buffer instead of the
+//              peer's FIFO slot.
+
+struct StepArgs {
+  const char* src;
+  char* dst;
+  char* sendDirect[3];
+  uint64_t nbytes;
+  int rmask, smask;
+  bool recvDirect;
+};
+
+template <int DT, int OP>
+__device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
+  if (c.tid == 0) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (ok && (a.smask & (1 << j))) ok = waitCounter(c, s[j].head, creditTarget(s[j].step));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (ok && (a.rmask & (1 << i))) ok = waitCounter(c, r[i].tail, r[i].step + 1);
+    if (a.rmask) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!ok) *c.sAbort = 1;
+  }
+  __syncthreads();
+  if (*(volatile int*)c.sAbort) return false;
+
+  PtrList in, out;
+  const uint64_t slotB = c.comm->slotBytes[PROTO_SIMPLE];
+  if (a.src) in.add(a.src);
+  if (a.recvDirect) {
+    if (a.smask) in.add(a.dst);  // forward what the peer stored into our buffer
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (a.rmask & (1 << i)) in.add(r[i].fifo + (r[i].step % NSLOTS) * slotB);
+    if (a.dst && !(a.src == a.dst && in.n == 1)) out.add(a.dst);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (a.smask & (1 << j)) out.add(a.sendDirect[j] ? a.sendDirect[j] : s[j].fifo + (s[j].step % NSLOTS) * slotB);
+  reduceCopyN<DT, OP>(c, in, out, a.nbytes);
+
+  drainVmem();
+  __syncthreads();
+  if (c.tid == 0) {
+    if (a.smask) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        if (a.smask & (1 << j)) stAgent(s[j].tail, s[j].step + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (a.rmask & (1 << i)) stAgent(r[i].head, r[i].step + 1);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (a.smask & (1 << j)) s[j].step++;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (a.rmask & (1 << i)) r[i].step++;
+  return true;
+}
+
+// Credit wait shared by LL and LL128: the slot about to be written must have
+// been consumed NSLOTS steps ago.
+__device__ __forceinline__ bool waitCredits(const Ctx& c, Conn* s, int smask) {
+  if (c.tid == 0) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (ok && (smask & (1 << j))) ok = waitCounter(c, s[j].head, creditTarget(s[j].step));
+    if (!ok) *c.sAbort = 1;
+  }
+  __syncthreads();
+  return !*(volatile int*)c.sAbort;
+}
+
+__device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, int rmask, int smask) {
+  drainVmem();
+  __syncthreads();
+  bool ok = !*(volatile int*)c.sAbort;
+  if (c.tid == 0 && ok) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (rmask & (1 << i)) stAgent(r[i].head, r[i].step + 1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (smask & (1 << j)) stAgent(s[j].tail, s[j].step + 1);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if (smask & (1 << j)) s[j].step++;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (rmask & (1 << i)) r[i].step++;
+  return ok;
+}
+
+// ------------------------------------------------------------------ LL datapath
+// A lane handles a pair of 8-byte units (8 payload bytes, 16 FIFO bytes).
+
+template <int DT, int OP>
+__device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
+  constexpr int E = ElemSize<DT>::value;
+  if (!waitCredits(c, s, a.smask)) return false;
+  const uint64_t slotB = c.comm->slotBytes[PROTO_LL];
+  const uint64_t npairs = (a.nbytes + 7) / 8;
+  uint64_t* rin[3];
+  uint64_t* sout[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rin[i] = (uint64_t*)(r[i].fifo + (r[i].step % NSLOTS) * slotB);
+    sout[i] = (uint64_t*)(s[i].fifo + (s[i].step % NSLOTS) * slotB);
+  }
+  const bool fast = (((uintptr_t)a.src | (uintptr_t)a.dst) & 7) == 0;
+  const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
+  bool alive = true;
+  for (uint64_t p = c.tid; p < npairs; p += c.nthreads) {
+    const uint64_t off = p * 8;
+    const int valid = (int)((a.nbytes - off) < 8 ? (a.nbytes - off) : 8);
+    uint32_t acc[2] = {0, 0};
+    bool have = false;
+    if (a.src) {
+      if (fast && valid == 8) {
+        const uint2 v = *(const uint2*)(a.src + off);
+        acc[0] = v.x;
+        acc[1] = v.y;
+      } else {
+        loadPart<E, 2>(a.src + off, valid, acc);
+      }
+      have = true;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (alive && (a.rmask & (1 << i))) {
+        const uint32_t flag = (uint32_t)(r[i].step + 1);
+        uint64_t u0 = ldAgent(rin[i] + 2 * p), u1 = ldAgent(rin[i] + 2 * p + 1);
+        Spinner sp;
+        while ((uint32_t)(u0 >> 32) != flag || (uint32_t)(u1 >> 32) != flag) {
+          if (!sp.tick(c)) { alive = false; break; }
+          u0 = ldAgent(rin[i] + 2 * p);
+          u1 = ldAgent(rin[i] + 2 * p + 1);
+        }
+        if (have) {
+          acc[0] = redWord<DT, OP>(acc[0], (uint32_t)u0);
+          acc[1] = redWord<DT, OP>(acc[1], (uint32_t)u1);
+        } else {
+          acc[0] = (uint32_t)u0;
+          acc[1] = (uint32_t)u1;
+          have = true;
+        }
+      }
+    }
+    if (!alive) break;
+    if (writeDst) {
+      if (fast && valid == 8) *(uint2*)(a.dst + off) = make_uint2(acc[0], acc[1]);
+      else storePart<E, 2>(a.dst + off, valid, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      if (a.smask & (1 << j)) {
+        const uint64_t flag = (uint64_t)(uint32_t)(s[j].step + 1) << 32;
+        stAgent(sout[j] + 2 * p, (uint64_t)acc[0] | flag);
+        stAgent(sout[j] + 2 * p + 1, (uint64_t)acc[1] | flag);
+      }
+    }
+  }
+  return finishFlagStep(c, r, s, a.rmask, a.smask);
+}
+
+// ------------------------------------------------------------------ LL128 datapath
+// Lane l of a wave handles 16 bytes (word pair l % 8) of line l / 8 of the
+// wave's group of 8 lines; lane 7 of each line carries 8 payload bytes and
+// the 8-byte flag.
+
+template <int DT, int OP>
+__device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
+  constexpr int E = ElemSize<DT>::value;
+  if (!waitCredits(c, s, a.smask)) return false;
+  const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL128];
+  const uint32_t nlines = (uint32_t)((a.nbytes + LL128_DATA - 1) / LL128_DATA);
+  __amdgpu_buffer_rsrc_t rin[3], sout[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    rin[i] = makeRsrc(r[i].fifo + (r[i].step % NSLOTS) * (uint64_t)slotB, slotB);
+    sout[i] = makeRsrc(s[i].fifo + (s[i].step % NSLOTS) * (uint64_t)slotB, slotB);
+  }
+  const bool fast = (((uintptr_t)a.src | (uintptr_t)a.dst) & 7) == 0;
+  const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
+  const int g = c.lid >> 3, j = c.lid & 7;
+  const int plen = (j < 7) ? 16 : 8;
+  bool alive = true;
+  for (uint32_t L0 = (uint32_t)c.wave * 8; L0 < nlines; L0 += (uint32_t)c.nwaves * 8) {
+    const uint32_t line = L0 + g;
+    const bool act = line < nlines;
+    const uint64_t payOff = (uint64_t)line * LL128_DATA + 16u * j;
+    const uint32_t loff = line * LL128_LINE + 16u * j;
+    int valid = 0;
+    if (act && payOff < a.nbytes) valid = (int)((a.nbytes - payOff) < (uint64_t)plen ? (a.nbytes - payOff) : plen);
+    uint32_t acc[4] = {0, 0, 0, 0};
+    bool have = false;
+    if (a.src) {
+      if (fast && valid == plen) {
+        const uint2 v0 = *(const uint2*)(a.src + payOff);
+        acc[0] = v0.x;
+        acc[1] = v0.y;
+        if (plen == 16) {
+          const uint2 v1 = *(const uint2*)(a.src + payOff + 8);
+          acc[2] = v1.x;
+          acc[3] = v1.y;
+        }
+      } else if (valid > 0) {
+        loadPart<E, 4>(a.src + payOff, valid, acc);
+      }
+      have = true;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (alive && (a.rmask & (1 << i))) {
+        const uint64_t flag = r[i].step + 1;
+        u32x4 v = act ? ldLine16(rin[i], loff) : u32x4{0, 0, 0, 0};
+        Spinner sp;
+        for (;;) {
+          // lane 7 of each line holds the flag; the whole line is re-read
+          // (one 8-lane load) until the flag is current
+          const int flagOk = (!act || j != 7 || ((((uint64_t)v.w << 32) | v.z) == flag)) ? 1 : 0;
+          const bool lineOk = __shfl(flagOk, c.lid | 7) != 0;
+          if (__all(lineOk)) break;
+          if (__any(!sp.tick(c))) { alive = false; break; }
+          if (!lineOk) v = ldLine16(rin[i], loff);
+        }
+        const uint32_t pw0 = v.x, pw1 = v.y, pw2 = (j < 7) ? v.z : 0u, pw3 = (j < 7) ? v.w : 0u;
+        if (have) {
+          acc[0] = redWord<DT, OP>(acc[0], pw0);
+          acc[1] = redWord<DT, OP>(acc[1], pw1);
+          acc[2] = redWord<DT, OP>(acc[2], pw2);
+          acc[3] = redWord<DT, OP>(acc[3], pw3);
+        } else {
+          acc[0] = pw0;
+          acc[1] = pw1;
+          acc[2] = pw2;
+          acc[3] = pw3;
+          have = true;
+        }
+      }
+    }
+    if (!alive) break;
+    if (writeDst && valid > 0) {
+      if (fast && valid == plen) {
+        *(uint2*)(a.dst + payOff) = make_uint2(acc[0], acc[1]);
+        if (plen == 16) *(uint2*)(a.dst + payOff + 8) = make_uint2(acc[2], acc[3]);
+      } else {
+        storePart<E, 4>(a.dst + payOff, valid, acc);
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (a.smask & (1 << q)) {
+          const uint64_t flag = s[q].step + 1;
+          u32x4 w = {acc[0], acc[1], acc[2], acc[3]};
+          if (j == 7) {
+            w.z = (uint32_t)flag;
+            w.w = (uint32_t)(flag >> 32);
+          }
+          stLine16(sout[q], loff, w);
+        }
+      }
+    }
+  }
+  if (!alive) atomicOr(c.sAbort, 1);
+  return finishFlagStep(c, r, s, a.rmask, a.smask);
+}
+
+template <int PROTO, int DT, int OP>
+__device__ __forceinline__ bool step(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
+  if constexpr (PROTO == PROTO_SIMPLE) return stepSimple<DT, OP>(c, r, s, a);
+  else if constexpr (PROTO == PROTO_LL) return stepLL<DT, OP>(c, r, s, a);
+  else return stepLL128<DT, OP>(c, r, s, a);
+}
+
+// ------------------------------------------------------------------ connections
+
+__device__ __forceinline__ uint64_t connId(const Ctx& c, int receiver, int kind) {
+  return ((uint64_t)c.lane * c.nranks + receiver) * NCONN + kind;
+}
+
+// Thread 0 reads the step counters (a receiver's own head, a sender's own
+// tail) and all threads pick them up from LDS.
+__device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, Conn* s, const int* speer,
+                           const int* skind, uint64_t* sSteps) {
+  const uint64_t fifoBytes = (uint64_t)NSLOTS * c.comm->slotBytes[proto];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (rkind[i] >= 0) {
+      uint64_t id = connId(c, c.rank, rkind[i]);
+      r[i].fifo = c.comm->fifo[proto] + id * fifoBytes;
+      r[i].tail = c.comm->ctr + id * CTR_RECORD_U64;
+      r[i].head = r[i].tail + CTR_HEAD_U64;
+    }
+    if (speer[i] >= 0) {
+      uint64_t id = connId(c, speer[i], skind[i]);
+      s[i].fifo = c.comm->fifo[proto] + id * fifoBytes;
+      s[i].tail = c.comm->ctr + id * CTR_RECORD_U64;
+      s[i].head = s[i].tail + CTR_HEAD_U64;
+    }
+  }
+  if (c.tid == 0) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sSteps[i] = rkind[i] >= 0 ? ldAgent(r[i].head) : 0;
+      sSteps[3 + i] = speer[i] >= 0 ? ldAgent(s[i].tail) : 0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    r[i].step = sSteps[i];
+    s[i].step = sSteps[3 + i];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint64_t ceilDiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+__device__ __forceinline__ uint64_t umin(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t roundUp(uint64_t a, uint64_t b) { return ceilDiv(a, b) * b; }
+
+// ------------------------------------------------------------------ algorithms
+
+// Ring AllReduce, Section V-E table: step 0 send, 1..k-2 recvReduceSend,
+// k-1 recvReduceCopySend, k..2k-3 recvCopySend, 2k-2 recv.  At step t rank p
+// works on segment (p - 1 - t) mod k of the loop.
+template <int PROTO, int DT, int OP>
+__device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  Conn r[3], s[3];
+  const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
+  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  const uint64_t E = w.elemBytes, A = 16 / E, K = w.chunk;
+  const uint64_t loopCount = (uint64_t)R * K;
+  const uint64_t full = w.chCount / loopCount, rem = w.chCount - full * loopCount;
+  const uint64_t nloops = full + (rem ? 1 : 0);
+  const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
+  const char* sendb = args.send[me];
+  char* recvb = args.recv[me];
+  char* nextRecv = args.recv[nxt];
+  for (uint64_t l = 0; l < nloops; ++l) {
+    const uint64_t base = l * loopCount;
+    const uint64_t Kl = (l < full) ? K : roundUp(ceilDiv(rem, R), A);
+    const uint64_t lim = (l < full) ? loopCount : rem;
+    for (int t = 0; t < 2 * R - 1; ++t) {
+      const int sidx = ((me - 1 - t) % R + 2 * R) % R;
+      const uint64_t a0 = umin(lim, (uint64_t)sidx * Kl), b0 = umin(lim, (uint64_t)(sidx + 1) * Kl);
+      const uint64_t off = (w.chOffset + base + a0) * E;
+      StepArgs a{};
+      a.nbytes = (b0 - a0) * E;
+      if (t == 0) {                         // send
+        a.src = sendb + off;
+        a.smask = 1;
+      } else if (t <= R - 2) {              // recvReduceSend
+        a.src = sendb + off;
+        a.rmask = 1;
+        a.smask = 1;
+      } else if (t == R - 1) {              // recvReduceCopySend
+        a.src = sendb + off;
+        a.dst = recvb + off;
+        a.rmask = 1;
+        a.smask = 1;
+        if (direct) a.sendDirect[0] = nextRecv + off;
+      } else if (t <= 2 * R - 3) {          // recvCopySend / directRecvCopySend
+        a.dst = recvb + off;
+        a.rmask = 1;
+        a.smask = 1;
+        if (direct) {
+          a.recvDirect = true;
+          a.sendDirect[0] = nextRecv + off;
+        }
+      } else {                              // recv / directRecv
+        a.dst = recvb + off;
+        a.rmask = 1;
+        a.recvDirect = direct;
+      }
+      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    }
+  }
+}
+
+// Ring ReduceScatter, Section V-E table: step 0 send, 1..k-2 recvReduceSend,
+// k-1 recvReduceCopy; at step t rank p works on block (p - 1 - t) mod k.
+template <int PROTO, int DT, int OP>
+__device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  Conn r[3], s[3];
+  const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
+  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  const uint64_t E = w.elemBytes, n = w.count, K = w.chunk;
+  const char* sendb = args.send[me];
+  char* recvb = args.recv[me];
+  for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
+    const uint64_t len = umin(K, w.chCount - a0);
+    for (int t = 0; t < R; ++t) {
+      const int blk = ((me - 1 - t) % R + 2 * R) % R;
+      StepArgs a{};
+      a.nbytes = len * E;
+      a.src = sendb + ((uint64_t)blk * n + w.chOffset + a0) * E;
+      a.rmask = t > 0 ? 1 : 0;
+      a.smask = t < R - 1 ? 1 : 0;
+      if (t == R - 1) a.dst = recvb + (w.chOffset + a0) * E;
+      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    }
+  }
+}
+
+// Ring AllGather, Section V-E table: step 0 copySend (send in place),
+// 1..k-2 recvCopySend, k-1 recv; at step t rank p handles block (p - t) mod k.
+// Units are bytes.
+template <int PROTO, int DT, int OP>
+__device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  Conn r[3], s[3];
+  const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
+  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  const uint64_t n = w.count, K = w.chunk;
+  const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
+  const char* sendb = args.send[me];
+  char* recvb = args.recv[me];
+  char* nextRecv = args.recv[nxt];
+  for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
+    const uint64_t len = umin(K, w.chCount - a0);
+    for (int t = 0; t < R; ++t) {
+      const int blk = ((me - t) % R + R) % R;
+      const uint64_t off = (uint64_t)blk * n + w.chOffset + a0;
+      StepArgs a{};
+      a.nbytes = len;
+      a.dst = recvb + off;
+      if (t == 0) {
+        a.src = sendb + w.chOffset + a0;
+        a.smask = 1;
+        if (direct) a.sendDirect[0] = nextRecv + off;
+      } else if (t <= R - 2) {
+        a.rmask = 1;
+        a.smask = 1;
+        if (direct) {
+          a.recvDirect = true;
+          a.sendDirect[0] = nextRecv + off;
+        }
+      } else {
+        a.rmask = 1;
+        a.recvDirect = direct;
+      }
+      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    }
+  }
+}
+
+// Ring Broadcast, Section V-E table: a chain root -> root+1 -> ... -> root-1;
+// root copySend (send in place), middle recvCopySend, last recv.  Bytes.
+template <int PROTO, int DT, int OP>
+__device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  const int pos = ((me - w.root) % R + R) % R;
+  Conn r[3], s[3];
+  const int rk[3] = {pos > 0 ? 0 : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1}, sk[3] = {0, -1, -1};
+  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  const uint64_t K = w.chunk;
+  const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
+  for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
+    const uint64_t len = umin(K, w.chCount - a0);
+    const uint64_t off = w.chOffset + a0;
+    StepArgs a{};
+    a.nbytes = len;
+    a.dst = args.recv[me] + off;
+    if (pos == 0) {
+      a.src = args.send[me] + off;
+      a.smask = 1;
+    } else {
+      a.rmask = 1;
+      a.recvDirect = direct;
+      if (pos < R - 1) a.smask = 1;
+    }
+    if (direct && a.smask) a.sendDirect[0] = args.recv[nxt] + off;
+    if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+  }
+}
+
+// Ring Reduce, Section V-E table: a chain root+1 -> ... -> root; initiator
+// send, middle recvReduceSend, root recvReduceCopy.
+template <int PROTO, int DT, int OP>
+__device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  const int pos = ((me - w.root - 1) % R + 2 * R) % R;
+  Conn r[3], s[3];
+  const int rk[3] = {pos > 0 ? 0 : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1}, sk[3] = {0, -1, -1};
+  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  const uint64_t E = w.elemBytes, K = w.chunk;
+  for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
+    const uint64_t len = umin(K, w.chCount - a0);
+    const uint64_t off = (w.chOffset + a0) * E;
+    StepArgs a{};
+    a.nbytes = len * E;
+    a.src = args.send[me] + off;
+    a.rmask = pos > 0 ? 1 : 0;
+    a.smask = pos < R - 1 ? 1 : 0;
+    if (pos == R - 1) a.dst = args.recv[me] + off;
+    if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+  }
+}
+
+// Tree AllReduce, Section V-E table: root recvReduceCopySend, middle
+// recvReduceSend then recvCopySend, leaf send then recv.  The reduction at a
+// node is op(op(local, first child), second child).  Chunk iterations are
+// software-pipelined: the upward step of chunk j precedes the downward step
+// of chunk j - (NSLOTS - 1), which cannot deadlock with NSLOTS slots.
+template <int PROTO, int DT, int OP>
+__device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int me = c.rank, t = w.tree;
+  const int par = c.comm->parent[t][me];
+  const int nk = c.comm->nchild[t][me];
+  const int k0 = c.comm->child[t][me][0], k1 = c.comm->child[t][me][1];
+  // receive side: 0,1 up from children; 2 down from parent
+  const int rk[3] = {nk > 0 ? 1 + 3 * t : -1, nk > 1 ? 2 + 3 * t : -1, par >= 0 ? 3 + 3 * t : -1};
+  // send side: 0 up to parent; 1,2 down to children
+  const int sp[3] = {par, nk > 0 ? k0 : -1, nk > 1 ? k1 : -1};
+  const int sk[3] = {par >= 0 ? 1 + 3 * t + c.comm->childIdx[t][me] : -1, 3 + 3 * t, 3 + 3 * t};
+  Conn r[3], s[3];
+  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  const int upR = (nk > 0 ? 1 : 0) | (nk > 1 ? 2 : 0);
+  const int downS = (nk > 0 ? 2 : 0) | (nk > 1 ? 4 : 0);
+  const uint64_t E = w.elemBytes, K = w.chunk;
+  const uint64_t nch = ceilDiv(w.chCount, K);
+  const uint64_t lag = NSLOTS - 1;
+  const char* sendb = args.send[me];
+  char* recvb = args.recv[me];
+  for (uint64_t j = 0; j < nch + lag; ++j) {
+    if (j < nch) {
+      const uint64_t a0 = j * K, len = umin(K, w.chCount - a0);
+      const uint64_t off = (w.chOffset + a0) * E;
+      StepArgs a{};
+      a.nbytes = len * E;
+      a.src = sendb + off;
+      a.rmask = upR;
+      if (par < 0) {             // root: recvReduceCopySend
+        a.dst = recvb + off;
+        a.smask = downS;
+      } else {                   // middle: recvReduceSend; leaf: send
+        a.smask = 1;
+      }
+      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    }
+    if (j >= lag && par >= 0) {
+      const uint64_t jd = j - lag, a0 = jd * K, len = umin(K, w.chCount - a0);
+      const uint64_t off = (w.chOffset + a0) * E;
+      StepArgs a{};
+      a.nbytes = len * E;
+      a.dst = recvb + off;
+      a.rmask = 4;
+      a.smask = downS;           // middle: recvCopySend; leaf: recv
+      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    }
+  }
+}
+
+template <int PROTO, int DT, int OP>
+__device__ __noinline__ void runItem(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  if constexpr (OP == OP_COPY) {
+    if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, DT, OP>(c, w, args, sSteps);
+    else if (w.coll == COLL_BROADCAST) ringBroadcast<PROTO, DT, OP>(c, w, args, sSteps);
+  } else {
+    if (w.coll == COLL_ALLREDUCE) {
+      if (w.algo == ALGO_TREE) treeAllReduce<PROTO, DT, OP>(c, w, args, sSteps);
+      else ringAllReduce<PROTO, DT, OP>(c, w, args, sSteps);
+    } else if (w.coll == COLL_REDUCESCATTER) {
+      ringReduceScatter<PROTO, DT, OP>(c, w, args, sSteps);
+    } else if (w.coll == COLL_REDUCE) {
+      ringReduce<PROTO, DT, OP>(c, w, args, sSteps);
+    }
+  }
+}
+
+template <int PROTO>
+__device__ void dispatchType(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  const int key = w.dtype * 4 + w.op;
+  switch (key) {
+    case DT_I32 * 4 + OP_SUM: runItem<PROTO, DT_I32, OP_SUM>(c, w, args, sSteps); break;
+    case DT_I32 * 4 + OP_MAX: runItem<PROTO, DT_I32, OP_MAX>(c, w, args, sSteps); break;
+    case DT_F32 * 4 + OP_SUM: runItem<PROTO, DT_F32, OP_SUM>(c, w, args, sSteps); break;
+    case DT_F32 * 4 + OP_MAX: runItem<PROTO, DT_F32, OP_MAX>(c, w, args, sSteps); break;
+    case DT_BF16 * 4 + OP_SUM: runItem<PROTO, DT_BF16, OP_SUM>(c, w, args, sSteps); break;
+    case DT_BF16 * 4 + OP_MAX: runItem<PROTO, DT_BF16, OP_MAX>(c, w, args, sSteps); break;
+    case DT_U8 * 4 + OP_COPY: runItem<PROTO, DT_U8, OP_COPY>(c, w, args, sSteps); break;
+    default: break;
+  }
+}
+
+// ------------------------------------------------------------------ kernel
+
+__global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
+  __shared__ WorkItem sItem;
+  __shared__ CollArgs sArgs;
+  __shared__ uint64_t sSteps[6];
+  __shared__ int sAbort;
+
+  const uint32_t R = d.nranks;
+  uint32_t lane, rank;
+  if (d.xcdMap) {
+    // workgroups are dispatched round-robin over the 8 XCDs; keep a lane's
+    // ranks on XCD (lane % 8) so its FIFO traffic stays in one L2
+    const uint32_t x = blockIdx.x & 7u, jj = blockIdx.x >> 3;
+    rank = jj % R;
+    lane = x + 8u * (jj / R);
+  } else {
+    lane = blockIdx.x / R;
+    rank = blockIdx.x % R;
+  }
+  if (lane >= d.nlanes) return;
+  const DevComm* comm = d.comm;
+  if ((comm->deadMask >> rank) & 1u) return;
+
+  Ctx c;
+  c.comm = comm;
+  c.rank = (int)rank;
+  c.lane = (int)lane;
+  c.nranks = (int)R;
+  c.tid = threadIdx.x;
+  c.nthreads = blockDim.x;
+  c.wave = threadIdx.x >> 6;
+  c.nwaves = (blockDim.x + 63) >> 6;
+  c.lid = threadIdx.x & 63;
+  c.sAbort = &sAbort;
+  if (threadIdx.x == 0) sAbort = 0;
+
+  const bool inl = d.items == nullptr;
+  const uint32_t first = inl ? lane : d.laneStart[lane];
+  const uint32_t last = inl ? lane + 1 : d.laneStart[lane + 1];
+  for (uint32_t it = first; it < last; ++it) {
+    __syncthreads();
+    const WorkItem* src = inl ? &d.inlineItems[it] : &d.items[it];
+    if (threadIdx.x < sizeof(WorkItem) / 4) ((uint32_t*)&sItem)[threadIdx.x] = ((const uint32_t*)src)[threadIdx.x];
+    __syncthreads();
+    const CollArgs* as = inl ? &d.inlineArgs : &d.args[sItem.argsIndex];
+    if (threadIdx.x < sizeof(CollArgs) / 8) ((uint64_t*)&sArgs)[threadIdx.x] = ((const uint64_t*)as)[threadIdx.x];
+    __syncthreads();
+    switch (sItem.proto) {
+      case PROTO_SIMPLE: dispatchType<PROTO_SIMPLE>(c, sItem, sArgs, sSteps); break;
+      case PROTO_LL: dispatchType<PROTO_LL>(c, sItem, sArgs, sSteps); break;
+      default: dispatchType<PROTO_LL128>(c, sItem, sArgs, sSteps); break;
+    }
+    __syncthreads();
+    if (*(volatile int*)&sAbort) break;
+    if (threadIdx.x == 0 && d.stamps && sItem.doneIndex != 0xFFFFFFFFu)
+      d.stamps[(uint64_t)sItem.doneIndex * R + rank] = nowTicks();
+  }
+}
+
+// ------------------------------------------------------------------ probes
+
+__global__ void xccProbeKernel(int* ids, int n) {
+  uint32_t x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+  if (threadIdx.x == 0 && (int)blockIdx.x < n) ids[blockIdx.x] = (int)(x & 0xF);
+}
+
+// LL128 tear probe: workgroup 2p writes, workgroup 2p+1 (or 2p+8: another
+// placement) reads `lines` lines per round.  Payload word q of line i in
+// round r is a hash of (r, i, q); a line whose flag is current but whose
+// payload differs is a torn line.  The writer waits for the reader's ack
+// before reusing the buffer.  Every wait is bounded by `maxTicks`.
+__device__ __forceinline__ uint32_t tearHash(uint32_t r, uint32_t i, uint32_t q) {
+  uint32_t h = r * 0x9E3779B1u ^ (i * 0x85EBCA77u) ^ (q * 0xC2B2AE3Du);
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 13;
+  return h;
+}
+
+__global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* acks, int pairs, int lines, int rounds,
+                                                        unsigned long long* counts, uint64_t maxTicks,
+                                                        uint32_t* failed) {
+  // pairing: writer w = blockIdx.x < pairs, reader = pairs + w
+  const int w = blockIdx.x % pairs;
+  const bool writer = (int)blockIdx.x < pairs;
+  if ((int)blockIdx.x >= 2 * pairs) return;
+  const uint32_t bytes = (uint32_t)lines * LL128_LINE;
+  __amdgpu_buffer_rsrc_t rs = makeRsrc(bufs + (uint64_t)w * bytes, bytes);
+  uint64_t* ack = acks + (uint64_t)w * 32;
+  const int lid = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int g = lid >> 3, j = lid & 7;
+  __shared__ int sFail;
+  if (threadIdx.x == 0) sFail = 0;
+  __syncthreads();
+  unsigned long long torn = 0, checked = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const uint64_t flag = (uint64_t)r + 1;
+    if (writer) {
+      if (threadIdx.x == 0) {
+        uint64_t t0 = nowTicks();
+        while (ldAgent(ack) < (uint64_t)r) {
+          __builtin_amdgcn_s_sleep(1);
+          if (nowTicks() - t0 > maxTicks) { sFail = 1; break; }
+        }
+      }
+      __syncthreads();
+      if (sFail) break;
+      for (int L0 = wave * 8; L0 < lines; L0 += nwaves * 8) {
+        const int line = L0 + g;
+        if (line < lines) {
+          u32x4 v = {tearHash(r, line, 4 * j), tearHash(r, line, 4 * j + 1), tearHash(r, line, 4 * j + 2),
+                     tearHash(r, line, 4 * j + 3)};
+          if (j == 7) {
+            v.z = (uint32_t)flag;
+            v.w = (uint32_t)(flag >> 32);
+          }
+          stLine16(rs, line * LL128_LINE + 16 * j, v);
+        }
+      }
+    } else {
+      for (int L0 = wave * 8; L0 < lines; L0 += nwaves * 8) {
+        const int line = L0 + g;
+        const bool act = line < lines;
+        const uint32_t loff = (uint32_t)line * LL128_LINE + 16u * j;
+        u32x4 v = act ? ldLine16(rs, loff) : u32x4{0, 0, 0, 0};
+        const uint64_t t0 = nowTicks();
+        bool tornSeen = false;
+        for (;;) {
+          const int flagOk = (!act || j != 7 || ((((uint64_t)v.w << 32) | v.z) == flag)) ? 1 : 0;
+          const bool lineOk = __shfl(flagOk, lid | 7) != 0;
+          const bool dataOk = !act || (v.x == tearHash(r, line, 4 * j) && v.y == tearHash(r, line, 4 * j + 1) &&
+                                       (j == 7 || (v.z == tearHash(r, line, 4 * j + 2) &&
+                                                   v.w == tearHash(r, line, 4 * j + 3))));
+          const unsigned long long okMask = __ballot(dataOk ? 1 : 0);
+          const bool lineData = ((okMask >> (lid & ~7)) & 0xFFull) == 0xFFull;
+          // a current flag with stale payload in any of the line's 8 lanes is a torn line
+          if (lineOk && !lineData && act && !tornSeen) {
+            tornSeen = true;
+            if (j == 0) torn++;
+          }
+          const bool done = lineOk && lineData;
+          if (__all(done)) break;
+          if (__any(nowTicks() - t0 > maxTicks)) { atomicOr(&sFail, 1); break; }
+          if (!done && act) v = ldLine16(rs, loff);
+        }
+        if (act && j == 0) checked++;
+        if (*(volatile int*)&sFail) break;
+      }
+      drainVmem();
+      __syncthreads();
+      if (sFail) break;
+      if (threadIdx.x == 0) stAgent(ack, (uint64_t)r + 1);
+    }
+  }
+  atomicAdd(&counts[0], torn);
+  atomicAdd(&counts[1], checked);
+  if (threadIdx.x == 0 && sFail) atomicOr(failed, 1u);
+}
+
+}  // namespace vccl
+
+// ------------------------------------------------------------------ host-side launchers
+// (called by the host runtime; plain C++ linkage inside the library)
+
+hipError_t vcclLaunchColl(const vccl::LaunchDesc& d, int grid, int block, hipStream_t stream, bool cooperative) {
+  void* args[] = {(void*)&d};
+  if (cooperative)
+    return hipLaunchCooperativeKernel((const void*)vccl::collKernel, dim3(grid), dim3(block), args, 0, stream);
+  return hipLaunchKernel((const void*)vccl::collKernel, dim3(grid), dim3(block), args, 0, stream);
+}
+
+hipError_t vcclCollOccupancy(int block, int* blocksPerCU) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocksPerCU, (const void*)vccl::collKernel, block, 0);
+}
+
+hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(vccl::xccProbeKernel, dim3(n), dim3(64), 0, stream, dIds, n);
+  return hipGetLastError();
+}
+
+hipError_t vcclLaunchTearProbe(char* bufs, uint64_t* acks, int pairs, int lines, int rounds, unsigned long long* counts,
+                               uint64_t maxTicks, uint32_t* failed, hipStream_t stream) {
+  void* args[] = {&bufs, &acks, &pairs, &lines, &rounds, &counts, &maxTicks, &failed};
+  return hipLaunchCooperativeKernel((const void*)vccl::tearProbeKernel, dim3(2 * pairs), dim3(256), args, 0, stream);
+}

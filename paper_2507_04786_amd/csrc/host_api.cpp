@@ -1,0 +1,520 @@
+// The C ABI: communicator management, per-rank call matching, group calls
+// (Section II-A) and the launch of one kernel per matched call or group.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "host_internal.h"
+
+using namespace vccl;
+
+namespace vccl {
+
+Clique* cliqueOf(vcclComm_t comm) { return comm ? comm->clique : nullptr; }
+int rankOf(vcclComm_t comm) { return comm ? comm->rank : -1; }
+
+namespace {
+
+struct GroupState {
+  int depth = 0;
+  std::vector<std::pair<Clique*, Coll>> colls;
+  std::vector<Clique*> touched;
+  vcclResult_t firstError = vcclSuccess;
+};
+thread_local GroupState tlsGroup;
+
+bool validHandle(vcclComm_t comm) { return comm && comm->clique && !comm->destroyed; }
+
+vcclResult_t asyncStatus(Clique* c) {
+  if (c->aborted) return vcclRemoteError;
+  const uint32_t e = __atomic_load_n(c->hError, __ATOMIC_ACQUIRE);
+  return e ? vcclRemoteError : vcclSuccess;
+}
+
+// Joins the streams of every rank involved: the launch stream waits for all
+// of them before the kernel, and all of them wait for the kernel after it.
+struct StreamSet {
+  hipStream_t list[2 * MAX_RANKS + 1];
+  int n = 0;
+  void add(hipStream_t s) {
+    for (int i = 0; i < n; ++i)
+      if (list[i] == s) return;
+    list[n++] = s;
+  }
+};
+
+vcclResult_t launchPrepared(Clique* c, LaunchDesc& d, int grid, int block, const StreamSet& ss) {
+  hipStream_t ls = ss.list[ss.n - 1];
+  int ev = 0;
+  // collectives of one set run in issue order: follow the previous launch
+  VCCL_HIPCHECK(hipStreamWaitEvent(ls, c->lastLaunchDone, 0));
+  for (int i = 0; i < ss.n - 1; ++i) {
+    VCCL_HIPCHECK(hipEventRecord(c->joinEvents[ev], ss.list[i]));
+    VCCL_HIPCHECK(hipStreamWaitEvent(ls, c->joinEvents[ev], 0));
+    ++ev;
+  }
+  hipError_t e = vcclLaunchColl(d, grid, block, ls, c->cooperative);
+  if (e != hipSuccess) {
+    logError("kernel launch", e, __FILE__, __LINE__);
+    return vcclUnhandledHipError;
+  }
+  VCCL_HIPCHECK(hipEventRecord(c->lastLaunchDone, ls));
+  for (int i = 0; i < ss.n - 1; ++i) VCCL_HIPCHECK(hipStreamWaitEvent(ss.list[i], c->lastLaunchDone, 0));
+  return vcclSuccess;
+}
+
+}  // namespace
+
+vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool grouped) {
+  vcclResult_t st = asyncStatus(c);
+  if (st != vcclSuccess) return st;
+  std::vector<Coll> colls;
+  for (const auto& x : collsIn)
+    if (x.count > 0) colls.push_back(x);
+  if (colls.empty()) return vcclSuccess;
+  const int R = c->nranks;
+  VCCL_HIPCHECK(hipSetDevice(c->device));
+
+  std::vector<Plan> plans(colls.size());
+  for (size_t g = 0; g < colls.size(); ++g) {
+    vcclResult_t r = planColl(c, colls[g], &plans[g]);
+    if (r != vcclSuccess) return r;
+  }
+  StreamSet ss;
+  for (const auto& x : colls)
+    for (int r = 0; r < R; ++r) ss.add(x.streams[r]);
+
+  vcclResult_t r = cliqueEnsureWorkCapacity(c, 0, 0, colls.size() * (size_t)R);
+  if (r != vcclSuccess) return r;
+
+  LaunchDesc d;
+  memset((void*)&d, 0, sizeof(d));
+  d.comm = c->dcomm;
+  d.nranks = (uint32_t)R;
+  d.xcdMap = (uint32_t)c->xcdMap;
+  d.stamps = c->dStamps;
+  int block = 64;
+  for (const auto& p : plans) block = std::max(block, p.nthreads);
+
+  int nlanes = 0;
+  size_t nitems = 0;
+  if (colls.size() == 1 && plans[0].nchannels <= MAX_INLINE) {
+    std::vector<WorkItem> items;
+    fillItems(c, colls[0], plans[0], 0, 0, &items);
+    d.items = nullptr;
+    d.inlineArgs = colls[0].args;
+    for (size_t i = 0; i < items.size(); ++i) d.inlineItems[i] = items[i];
+    nlanes = (int)items.size();
+    nitems = items.size();
+  } else {
+    // work list: every collective's channel items placed on lanes, longest
+    // first onto the least-loaded lane; each lane keeps issue order
+    std::vector<WorkItem> items;
+    for (size_t g = 0; g < colls.size(); ++g) fillItems(c, colls[g], plans[g], (uint32_t)g, (uint32_t)g, &items);
+    const int occ = cliqueOccupancy(c, block);
+    int capLanes = c->xcdMap ? (c->numCUs * occ / (8 * R)) * 8 : c->numCUs * occ / R;
+    capLanes = std::max(1, std::min(capLanes, c->maxLanes));
+    int maxCh = 1;
+    for (const auto& p : plans) maxCh = std::max(maxCh, p.nchannels);
+    nlanes = std::min<int>(capLanes, std::max<int>(maxCh, std::min<int>((int)items.size(), c->maxLanes)));
+    std::vector<double> cost(items.size());
+    for (size_t i = 0; i < items.size(); ++i) cost[i] = estimateCost(c, items[i]);
+    std::vector<size_t> order(items.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<double> load(nlanes, 0.0);
+    std::vector<int> laneOf(items.size());
+    for (size_t k : order) {
+      int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      laneOf[k] = best;
+      load[best] += cost[k];
+    }
+    std::vector<std::vector<uint32_t>> perLane(nlanes);
+    for (size_t i = 0; i < items.size(); ++i) perLane[laneOf[i]].push_back((uint32_t)i);
+    r = cliqueEnsureWorkCapacity(c, items.size(), colls.size(), colls.size() * (size_t)R);
+    if (r != vcclSuccess) return r;
+    // stage: items (lane order), laneStart, args -> pinned buffer -> device
+    const int k = c->stageNext;
+    c->stageNext ^= 1;
+    VCCL_HIPCHECK(hipEventSynchronize(c->stageEvent[k]));
+    char* stage = (char*)c->hStage[k];
+    WorkItem* sItems = (WorkItem*)stage;
+    uint32_t* sLane = (uint32_t*)(stage + items.size() * sizeof(WorkItem));
+    CollArgs* sArgs = (CollArgs*)(stage + items.size() * sizeof(WorkItem) + (MAX_LANES + 1) * sizeof(uint32_t));
+    uint32_t pos = 0;
+    for (int l = 0; l < nlanes; ++l) {
+      sLane[l] = pos;
+      for (uint32_t i : perLane[l]) sItems[pos++] = items[i];
+    }
+    sLane[nlanes] = pos;
+    for (size_t g = 0; g < colls.size(); ++g) sArgs[g] = colls[g].args;
+    hipStream_t ls = ss.list[ss.n - 1];
+    VCCL_HIPCHECK(hipStreamWaitEvent(ls, c->lastLaunchDone, 0));
+    VCCL_HIPCHECK(hipMemcpyAsync(c->dItems, sItems, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, ls));
+    VCCL_HIPCHECK(hipMemcpyAsync(c->dLaneStart, sLane, (nlanes + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, ls));
+    VCCL_HIPCHECK(hipMemcpyAsync(c->dArgs, sArgs, colls.size() * sizeof(CollArgs), hipMemcpyHostToDevice, ls));
+    VCCL_HIPCHECK(hipEventRecord(c->stageEvent[k], ls));
+    d.items = c->dItems;
+    d.laneStart = c->dLaneStart;
+    d.args = c->dArgs;
+    d.stamps = c->dStamps;
+    nitems = items.size();
+  }
+  d.nlanes = (uint32_t)nlanes;
+  const int grid = c->xcdMap ? 8 * R * ((nlanes + 7) / 8) : R * nlanes;
+  const int occ = cliqueOccupancy(c, block);
+  if (grid > c->numCUs * occ) return vcclInternalError;
+  r = launchPrepared(c, d, grid, block, ss);
+  if (r != vcclSuccess) return r;
+  c->lastStampColls = (int)colls.size();
+  vcclPlanInfo_t& info = c->lastPlan;
+  info.algo = plans[0].algo;
+  info.proto = plans[0].proto;
+  info.nchannels = plans[0].nchannels;
+  info.nthreads = block;
+  info.direct = plans[0].direct;
+  info.chunkBytes = (size_t)plans[0].chunkBytes;
+  info.nlanes = nlanes;
+  info.nitems = (int)nitems;
+  info.ncolls = (int)colls.size();
+  info.grid = grid;
+  (void)grouped;
+  return vcclSuccess;
+}
+
+}  // namespace vccl
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* vcclGetErrorString(vcclResult_t r) {
+  switch (r) {
+    case vcclSuccess: return "no error";
+    case vcclUnhandledHipError: return "unhandled HIP error";
+    case vcclSystemError: return "system error";
+    case vcclInternalError: return "internal error";
+    case vcclInvalidArgument: return "invalid argument";
+    case vcclInvalidUsage: return "invalid usage";
+    case vcclRemoteError: return "remote error (peer timeout or abort)";
+    case vcclInProgress: return "operation in progress";
+  }
+  return "unknown result";
+}
+
+vcclResult_t vcclGetVersion(int* version) {
+  if (!version) return vcclInvalidArgument;
+  *version = VCCL_MAJOR * 100 + VCCL_MINOR;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist) {
+  if (!comms || nranks < 2 || nranks > VCCL_MAX_RANKS) return vcclInvalidArgument;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return vcclUnhandledHipError;
+  int dev = 0;
+  if (devlist) {
+    dev = devlist[0];
+    for (int i = 1; i < nranks; ++i)
+      if (devlist[i] != dev) return vcclInvalidArgument;
+  } else {
+    if (hipGetDevice(&dev) != hipSuccess) return vcclUnhandledHipError;
+  }
+  if (dev < 0 || dev >= ndev) return vcclInvalidArgument;
+  Clique* c = nullptr;
+  vcclResult_t r = cliqueCreate(nranks, dev, &c);
+  if (r != vcclSuccess) return r;
+  for (int i = 0; i < nranks; ++i) {
+    vcclComm* h = new vcclComm{c, i, false};
+    c->handles.push_back(h);
+    comms[i] = h;
+  }
+  logInfo("init %d virtual ranks on device %d, %d channels max", nranks, dev, c->maxLanes);
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommDestroy(vcclComm_t comm) {
+  if (!validHandle(comm)) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  comm->destroyed = true;
+  if (++c->destroyedHandles == c->nranks) cliqueFree(c);
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommAbort(vcclComm_t comm) {
+  if (!validHandle(comm)) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  __atomic_store_n(c->hAbort, 1u, __ATOMIC_RELEASE);
+  c->aborted = true;
+  for (auto& q : c->pending) q.clear();
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommGetAsyncError(vcclComm_t comm, vcclResult_t* asyncError) {
+  if (!validHandle(comm) || !asyncError) return vcclInvalidArgument;
+  *asyncError = asyncStatus(comm->clique);
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommCount(vcclComm_t comm, int* count) {
+  if (!validHandle(comm) || !count) return vcclInvalidArgument;
+  *count = comm->clique->nranks;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommUserRank(vcclComm_t comm, int* rank) {
+  if (!validHandle(comm) || !rank) return vcclInvalidArgument;
+  *rank = comm->rank;
+  return vcclSuccess;
+}
+
+static vcclResult_t enqueueCall(vcclComm_t comm, const Call& call) {
+  if (!validHandle(comm)) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  if (c->aborted) return vcclRemoteError;
+  const int R = c->nranks;
+  if (call.dtype < vcclInt32 || call.dtype > vcclBfloat16) return vcclInvalidArgument;
+  const bool reduces = call.coll == COLL_ALLREDUCE || call.coll == COLL_REDUCE || call.coll == COLL_REDUCESCATTER;
+  if (reduces && (call.op < vcclSum || call.op > vcclMax)) return vcclInvalidArgument;
+  const bool rooted = call.coll == COLL_BROADCAST || call.coll == COLL_REDUCE;
+  if (rooted && (call.root < 0 || call.root >= R)) return vcclInvalidArgument;
+  const size_t E = dtypeBytes(call.dtype);
+  const int me = comm->rank;
+  const bool needSend = !(call.coll == COLL_BROADCAST && me != call.root);
+  const bool needRecv = !(call.coll == COLL_REDUCE && me != call.root);
+  if (call.count > 0) {
+    if (needSend && !call.send) return vcclInvalidArgument;
+    if (needRecv && !call.recv) return vcclInvalidArgument;
+  }
+  if (((uintptr_t)call.send % E) || ((uintptr_t)call.recv % E)) return vcclInvalidArgument;
+  if (call.count > ((size_t)1 << 40)) return vcclInvalidArgument;
+  c->pending[me].push_back(call);
+  for (int r = 0; r < R; ++r)
+    if (c->pending[r].empty()) return vcclSuccess;  // wait for the other ranks
+  Coll coll{};
+  const Call& f = c->pending[0].front();
+  coll.coll = f.coll;
+  coll.dtype = f.dtype;
+  coll.op = f.op;
+  coll.root = f.root;
+  coll.count = f.count;
+  vcclResult_t mismatch = vcclSuccess;
+  for (int r = 0; r < R; ++r) {
+    const Call& x = c->pending[r].front();
+    if (x.coll != f.coll || x.count != f.count || x.dtype != f.dtype || (reduces && x.op != f.op) ||
+        (rooted && x.root != f.root))
+      mismatch = vcclInvalidUsage;
+    coll.args.send[r] = (const char*)x.send;
+    coll.args.recv[r] = (char*)x.recv;
+    coll.streams[r] = x.stream;
+  }
+  for (int r = 0; r < R; ++r) c->pending[r].pop_front();
+  if (mismatch != vcclSuccess) return mismatch;
+  if (tlsGroup.depth > 0) {
+    tlsGroup.colls.push_back({c, coll});
+    if (std::find(tlsGroup.touched.begin(), tlsGroup.touched.end(), c) == tlsGroup.touched.end())
+      tlsGroup.touched.push_back(c);
+    return vcclSuccess;
+  }
+  std::vector<Coll> one{coll};
+  return launchColls(c, one, false);
+}
+
+vcclResult_t vcclAllReduce(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype,
+                           vcclRedOp_t op, vcclComm_t comm, void* stream) {
+  Call x{COLL_ALLREDUCE, (int)datatype, (int)op, 0, count, sendbuff, recvbuff, (hipStream_t)stream};
+  return enqueueCall(comm, x);
+}
+
+vcclResult_t vcclBroadcast(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype, int root,
+                           vcclComm_t comm, void* stream) {
+  Call x{COLL_BROADCAST, (int)datatype, (int)vcclSum, root, count, sendbuff, recvbuff, (hipStream_t)stream};
+  return enqueueCall(comm, x);
+}
+
+vcclResult_t vcclReduce(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype,
+                        vcclRedOp_t op, int root, vcclComm_t comm, void* stream) {
+  Call x{COLL_REDUCE, (int)datatype, (int)op, root, count, sendbuff, recvbuff, (hipStream_t)stream};
+  return enqueueCall(comm, x);
+}
+
+vcclResult_t vcclAllGather(const void* sendbuff, void* recvbuff, size_t sendcount, vcclDataType_t datatype,
+                           vcclComm_t comm, void* stream) {
+  Call x{COLL_ALLGATHER, (int)datatype, (int)vcclSum, 0, sendcount, sendbuff, recvbuff, (hipStream_t)stream};
+  return enqueueCall(comm, x);
+}
+
+vcclResult_t vcclReduceScatter(const void* sendbuff, void* recvbuff, size_t recvcount, vcclDataType_t datatype,
+                               vcclRedOp_t op, vcclComm_t comm, void* stream) {
+  Call x{COLL_REDUCESCATTER, (int)datatype, (int)op, 0, recvcount, sendbuff, recvbuff, (hipStream_t)stream};
+  return enqueueCall(comm, x);
+}
+
+vcclResult_t vcclGroupStart(void) {
+  ++tlsGroup.depth;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclGroupEnd(void) {
+  if (tlsGroup.depth <= 0) return vcclInvalidUsage;
+  if (--tlsGroup.depth > 0) return vcclSuccess;
+  vcclResult_t result = vcclSuccess;
+  std::vector<Clique*> touched;
+  touched.swap(tlsGroup.touched);
+  auto colls = std::move(tlsGroup.colls);
+  tlsGroup.colls.clear();
+  for (Clique* c : touched) {
+    bool incomplete = false;
+    for (auto& q : c->pending)
+      if (!q.empty()) incomplete = true;
+    if (incomplete) {
+      for (auto& q : c->pending) q.clear();
+      result = vcclInvalidUsage;
+      continue;
+    }
+    std::vector<Coll> mine;
+    for (auto& pc : colls)
+      if (pc.first == c) mine.push_back(pc.second);
+    vcclResult_t r = launchColls(c, mine, true);
+    if (r != vcclSuccess && result == vcclSuccess) result = r;
+  }
+  return result;
+}
+
+vcclResult_t vcclCommSetTuning(vcclComm_t comm, const vcclTuning_t* t) {
+  if (!validHandle(comm) || !t) return vcclInvalidArgument;
+  if (t->algo < -1 || t->algo > 1 || t->proto < -1 || t->proto > 2) return vcclInvalidArgument;
+  if (t->nchannels < 0 || t->nchannels > VCCL_MAX_CHANNELS) return vcclInvalidArgument;
+  if (t->nthreads != 0 && (t->nthreads < 64 || t->nthreads > 1024 || t->nthreads % 64)) return vcclInvalidArgument;
+  if (t->chunkBytes % 16) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  if (t->nchannels > c->maxLanes) return vcclInvalidArgument;
+  c->apiTune.algo = t->algo;
+  c->apiTune.proto = t->proto;
+  c->apiTune.nchannels = t->nchannels;
+  c->apiTune.nthreads = t->nthreads;
+  c->apiTune.chunkBytes = t->chunkBytes;
+  c->apiTune.direct = t->direct;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info) {
+  if (!validHandle(comm) || !info) return vcclInvalidArgument;
+  *info = comm->clique->lastPlan;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int n, int* written) {
+  if (!validHandle(comm) || !stamps_ns || !written) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  const int R = c->nranks;
+  const int nc = std::min(n, c->lastStampColls);
+  *written = 0;
+  if (nc <= 0) return vcclSuccess;
+  VCCL_HIPCHECK(hipEventSynchronize(c->lastLaunchDone));
+  std::vector<uint64_t> raw((size_t)nc * R);
+  VCCL_HIPCHECK(hipMemcpy(raw.data(), c->dStamps, raw.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  for (int g = 0; g < nc; ++g) {
+    uint64_t m = 0;
+    for (int r = 0; r < R; ++r) m = std::max(m, raw[(size_t)g * R + r]);
+    stamps_ns[g] = (uint64_t)((double)m / c->ticksPerUs * 1000.0);
+  }
+  *written = nc;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommSetTimeout(vcclComm_t comm, uint64_t timeout_us) {
+  if (!validHandle(comm) || timeout_us == 0) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  VCCL_HIPCHECK(hipSetDevice(c->device));
+  VCCL_HIPCHECK(hipDeviceSynchronize());
+  c->host.timeoutTicks = (uint64_t)((double)timeout_us * c->ticksPerUs);
+  VCCL_HIPCHECK(hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice));
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommDebugSetDeadRanks(vcclComm_t comm, uint32_t mask) {
+  if (!validHandle(comm)) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  VCCL_HIPCHECK(hipSetDevice(c->device));
+  VCCL_HIPCHECK(hipDeviceSynchronize());
+  c->host.deadMask = mask;
+  VCCL_HIPCHECK(hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice));
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int proto, size_t offset, void* dst,
+                                   size_t bytes) {
+  if (!validHandle(comm) || !dst) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  if (channel < 0 || channel >= c->maxLanes || rank < 0 || rank >= c->nranks || proto < 0 || proto > 2)
+    return vcclInvalidArgument;
+  const uint64_t fifoBytes = (uint64_t)NSLOTS * c->host.slotBytes[proto];
+  if (offset + bytes > fifoBytes) return vcclInvalidArgument;
+  const uint64_t id = ((uint64_t)channel * c->nranks + rank) * NCONN + 0;
+  VCCL_HIPCHECK(hipSetDevice(c->device));
+  VCCL_HIPCHECK(hipDeviceSynchronize());
+  VCCL_HIPCHECK(hipMemcpy(dst, c->fifo[proto] + id * fifoBytes + offset, bytes, hipMemcpyDeviceToHost));
+  return vcclSuccess;
+}
+
+vcclResult_t vcclProbeXccIds(int n, int* ids) {
+  if (n <= 0 || !ids) return vcclInvalidArgument;
+  int* d = nullptr;
+  VCCL_HIPCHECK(hipMalloc((void**)&d, n * sizeof(int)));
+  hipError_t e = vcclLaunchXccProbe(d, n, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(ids, d, n * sizeof(int), hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) {
+    logError("xcc probe", e, __FILE__, __LINE__);
+    return vcclUnhandledHipError;
+  }
+  return vcclSuccess;
+}
+
+vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, uint64_t* torn, uint64_t* checked) {
+  if (pairs < 1 || pairs > 64 || lines < 1 || lines > 65536 || rounds < 1 || !torn || !checked)
+    return vcclInvalidArgument;
+  char* bufs = nullptr;
+  uint64_t* acks = nullptr;
+  unsigned long long* counts = nullptr;
+  uint32_t* failed = nullptr;
+  const size_t bytes = (size_t)pairs * lines * LL128_LINE;
+  VCCL_HIPCHECK(hipMalloc((void**)&bufs, bytes));
+  VCCL_HIPCHECK(hipMalloc((void**)&acks, (size_t)pairs * 32 * sizeof(uint64_t)));
+  VCCL_HIPCHECK(hipMalloc((void**)&counts, 2 * sizeof(unsigned long long)));
+  VCCL_HIPCHECK(hipMalloc((void**)&failed, sizeof(uint32_t)));
+  VCCL_HIPCHECK(hipMemset(bufs, 0, bytes));
+  VCCL_HIPCHECK(hipMemset(acks, 0, (size_t)pairs * 32 * sizeof(uint64_t)));
+  VCCL_HIPCHECK(hipMemset(counts, 0, 2 * sizeof(unsigned long long)));
+  VCCL_HIPCHECK(hipMemset(failed, 0, sizeof(uint32_t)));
+  int dev = 0, wallKHz = 100000;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, dev);
+  const uint64_t maxTicks = (uint64_t)wallKHz * 1000ull * 5ull;  // 5 s per wait
+  hipError_t e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  unsigned long long h[2] = {0, 0};
+  uint32_t hf = 0;
+  if (e == hipSuccess) e = hipMemcpy(h, counts, sizeof(h), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&hf, failed, sizeof(hf), hipMemcpyDeviceToHost);
+  hipFree(bufs);
+  hipFree(acks);
+  hipFree(counts);
+  hipFree(failed);
+  if (e != hipSuccess) {
+    logError("tear probe", e, __FILE__, __LINE__);
+    return vcclUnhandledHipError;
+  }
+  *torn = h[0];
+  *checked = h[1];
+  return hf ? vcclRemoteError : vcclSuccess;
+}
+
+}  // extern "C"

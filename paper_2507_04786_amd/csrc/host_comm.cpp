@@ -1,0 +1,271 @@
+// Communicator sets: FIFO and counter allocation, ring and double binary tree
+// (Section II-C), occupancy, staging buffers.
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "host_internal.h"
+
+namespace vccl {
+
+void logError(const char* what, hipError_t e, const char* file, int line) {
+  fprintf(stderr, "vccl: %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+}
+
+void logInfo(const char* fmt, ...) {
+  static int level = -1;
+  if (level < 0) {
+    std::string v = envStr("VCCL_DEBUG");
+    level = (v == "INFO" || v == "TRACE") ? 1 : 0;
+  }
+  if (!level) return;
+  va_list ap;
+  va_start(ap, fmt);
+  fprintf(stderr, "vccl: ");
+  vfprintf(stderr, fmt, ap);
+  fprintf(stderr, "\n");
+  va_end(ap);
+}
+
+std::string envStr(const char* name) {
+  const char* v = getenv(name);
+  return v ? std::string(v) : std::string();
+}
+
+long envLong(const char* name, long dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  char* end = nullptr;
+  long x = strtol(v, &end, 0);
+  return (end && *end == '\0') ? x : dflt;
+}
+
+// Double binary tree.  The paper fixes only its properties (no rank inner in
+// both trees, at most one rank a leaf in both; the second tree mirrors the
+// first for an even rank count, shifts it by one position for an odd one).
+// Tree 0 over positions 0..R-1: position 0 is the root with one child, the
+// largest power of two below R; position q (lowest set bit b) has parent
+// (q - b) | 2b, or q - b when that is >= R; its children are q - b/2 and the
+// first of q + b/2, q + b/4, ..., q + 1 below R.
+void buildTrees(int R, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2], int8_t childIdx[2][MAX_RANKS],
+                int8_t nchild[2][MAX_RANKS]) {
+  int pPar[MAX_RANKS], pKids[MAX_RANKS][2], pN[MAX_RANKS];
+  for (int q = 0; q < R; ++q) {
+    pPar[q] = -1;
+    pN[q] = 0;
+    pKids[q][0] = pKids[q][1] = -1;
+  }
+  int top = 1;
+  while (top * 2 < R) top *= 2;
+  if (R > 1) {
+    pKids[0][0] = top;
+    pN[0] = 1;
+  }
+  for (int q = 1; q < R; ++q) {
+    int b = q & -q;
+    int up = (q - b) | (2 * b);
+    if (up >= R) up = q - b;
+    pPar[q] = up;
+    if (b > 1) {
+      pKids[q][pN[q]++] = q - b / 2;
+      for (int h = b / 2; h >= 1; h /= 2) {
+        if (q + h < R) {
+          pKids[q][pN[q]++] = q + h;
+          break;
+        }
+      }
+    }
+  }
+  for (int t = 0; t < 2; ++t) {
+    int rankAt[MAX_RANKS];
+    for (int q = 0; q < R; ++q) rankAt[q] = (t == 0) ? q : ((R % 2 == 0) ? R - 1 - q : (q + 1) % R);
+    for (int q = 0; q < R; ++q) {
+      int r = rankAt[q];
+      parent[t][r] = (int8_t)(pPar[q] < 0 ? -1 : rankAt[pPar[q]]);
+      nchild[t][r] = (int8_t)pN[q];
+      child[t][r][0] = (int8_t)(pN[q] > 0 ? rankAt[pKids[q][0]] : -1);
+      child[t][r][1] = (int8_t)(pN[q] > 1 ? rankAt[pKids[q][1]] : -1);
+      childIdx[t][r] = 0;
+    }
+    for (int r = 0; r < R; ++r)
+      for (int k = 0; k < nchild[t][r]; ++k) childIdx[t][child[t][r][k]] = (int8_t)k;
+  }
+}
+
+vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
+  Clique* c = new Clique();
+  c->nranks = nranks;
+  c->device = device;
+  c->maxLanes = (int)envLong("VCCL_MAX_CHANNELS", 16);
+  if (c->maxLanes < 1) c->maxLanes = 1;
+  if (c->maxLanes > MAX_LANES) c->maxLanes = MAX_LANES;
+  c->pending.resize(nranks);
+  auto fail = [&](hipError_t e, const char* what) {
+    logError(what, e, __FILE__, __LINE__);
+    cliqueFree(c);
+    return vcclUnhandledHipError;
+  };
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail(e, "hipGetDeviceProperties");
+  c->numCUs = prop.multiProcessorCount;
+  int wallKHz = 0;
+  if (hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, device) == hipSuccess && wallKHz > 0)
+    c->ticksPerUs = wallKHz / 1000.0;
+
+  const uint64_t nconn = (uint64_t)c->maxLanes * nranks * NCONN;
+  const uint64_t slot[3] = {(uint64_t)envLong("VCCL_SIMPLE_SLOT_BYTES", SLOT_BYTES_SIMPLE), SLOT_BYTES_LL,
+                            SLOT_BYTES_LL128};
+  for (int p = 0; p < 3; ++p) {
+    const uint64_t bytes = nconn * NSLOTS * slot[p];
+    e = hipMalloc((void**)&c->fifo[p], bytes);
+    if (e != hipSuccess) return fail(e, "hipMalloc(fifo)");
+    if (p != PROTO_SIMPLE) {
+      // flags start at 0; the first flag a receiver waits for is 1
+      e = hipMemset(c->fifo[p], 0, bytes);
+      if (e != hipSuccess) return fail(e, "hipMemset(fifo)");
+    }
+    c->host.fifo[p] = c->fifo[p];
+    c->host.slotBytes[p] = slot[p];
+  }
+  e = hipMalloc((void**)&c->ctr, nconn * CTR_RECORD_U64 * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(e, "hipMalloc(counters)");
+  e = hipMemset(c->ctr, 0, nconn * CTR_RECORD_U64 * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(e, "hipMemset(counters)");
+  e = hipHostMalloc((void**)&c->hAbort, 256, hipHostMallocCoherent);
+  if (e != hipSuccess) return fail(e, "hipHostMalloc(abort)");
+  e = hipHostMalloc((void**)&c->hError, 256, hipHostMallocCoherent);
+  if (e != hipSuccess) return fail(e, "hipHostMalloc(error)");
+  *c->hAbort = 0;
+  *c->hError = 0;
+
+  c->host.nranks = nranks;
+  c->host.maxLanes = c->maxLanes;
+  const double timeoutUs = (double)envLong("VCCL_TIMEOUT_US", 5000000);
+  c->host.timeoutTicks = (uint64_t)(timeoutUs * c->ticksPerUs);
+  c->host.deadMask = 0;
+  c->host.ctr = c->ctr;
+  c->host.abortFlag = c->hAbort;
+  c->host.errorWord = c->hError;
+  memset(c->host.parent, -1, sizeof(c->host.parent));
+  memset(c->host.child, -1, sizeof(c->host.child));
+  buildTrees(nranks, c->host.parent, c->host.child, c->host.childIdx, c->host.nchild);
+  e = hipMalloc((void**)&c->dcomm, sizeof(DevComm));
+  if (e != hipSuccess) return fail(e, "hipMalloc(devcomm)");
+  e = hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(e, "hipMemcpy(devcomm)");
+  e = hipEventCreateWithFlags(&c->lastLaunchDone, hipEventDisableTiming);
+  if (e != hipSuccess) return fail(e, "hipEventCreate");
+  for (int i = 0; i < 2; ++i) {
+    e = hipEventCreateWithFlags(&c->stageEvent[i], hipEventDisableTiming);
+    if (e != hipSuccess) return fail(e, "hipEventCreate");
+  }
+  c->joinEvents.resize(2 * MAX_RANKS + 2, nullptr);
+  for (auto& ev : c->joinEvents) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(e, "hipEventCreate");
+  }
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(e, "hipDeviceSynchronize");
+
+  // tuning from the environment (overridden by vcclCommSetTuning)
+  std::string a = envStr("VCCL_ALGO"), p = envStr("VCCL_PROTO");
+  if (a == "ring" || a == "Ring") c->envTune.algo = ALGO_RING;
+  if (a == "tree" || a == "Tree") c->envTune.algo = ALGO_TREE;
+  if (p == "simple" || p == "Simple") c->envTune.proto = PROTO_SIMPLE;
+  if (p == "ll" || p == "LL") c->envTune.proto = PROTO_LL;
+  if (p == "ll128" || p == "LL128") c->envTune.proto = PROTO_LL128;
+  c->envTune.nchannels = (int)envLong("VCCL_NCHANNELS", 0);
+  c->envTune.nthreads = (int)envLong("VCCL_NTHREADS", 0);
+  c->envTune.chunkBytes = (uint64_t)envLong("VCCL_CHUNK_BYTES", 0);
+  c->envTune.direct = (int)envLong("VCCL_DIRECT", -1);
+  c->cooperative = envStr("VCCL_LAUNCH") != "plain";
+  c->xcdMap = (int)envLong("VCCL_XCD_MAP", 1);
+  *out = c;
+  return vcclSuccess;
+}
+
+void cliqueFree(Clique* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (int p = 0; p < 3; ++p)
+    if (c->fifo[p]) hipFree(c->fifo[p]);
+  if (c->ctr) hipFree(c->ctr);
+  if (c->dcomm) hipFree(c->dcomm);
+  if (c->dItems) hipFree(c->dItems);
+  if (c->dLaneStart) hipFree(c->dLaneStart);
+  if (c->dArgs) hipFree(c->dArgs);
+  if (c->dStamps) hipFree(c->dStamps);
+  for (int i = 0; i < 2; ++i) {
+    if (c->hStage[i]) hipHostFree(c->hStage[i]);
+    if (c->stageEvent[i]) hipEventDestroy(c->stageEvent[i]);
+  }
+  if (c->lastLaunchDone) hipEventDestroy(c->lastLaunchDone);
+  for (auto ev : c->joinEvents)
+    if (ev) hipEventDestroy(ev);
+  if (c->hAbort) hipHostFree(c->hAbort);
+  if (c->hError) hipHostFree(c->hError);
+  for (auto* h : c->handles) delete h;
+  delete c;
+}
+
+vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps) {
+  if (items > c->itemCap) {
+    size_t cap = items < 256 ? 256 : items * 2;
+    if (c->dItems) {
+      VCCL_HIPCHECK(hipDeviceSynchronize());
+      VCCL_HIPCHECK(hipFree(c->dItems));
+      VCCL_HIPCHECK(hipFree(c->dLaneStart));
+    }
+    VCCL_HIPCHECK(hipMalloc((void**)&c->dItems, cap * sizeof(WorkItem)));
+    VCCL_HIPCHECK(hipMalloc((void**)&c->dLaneStart, (MAX_LANES + 1) * sizeof(uint32_t)));
+    c->itemCap = cap;
+  }
+  if (args > c->argCap) {
+    size_t cap = args < 128 ? 128 : args * 2;
+    if (c->dArgs) {
+      VCCL_HIPCHECK(hipDeviceSynchronize());
+      VCCL_HIPCHECK(hipFree(c->dArgs));
+    }
+    VCCL_HIPCHECK(hipMalloc((void**)&c->dArgs, cap * sizeof(CollArgs)));
+    c->argCap = cap;
+  }
+  const size_t stage = c->itemCap * sizeof(WorkItem) + (MAX_LANES + 1) * sizeof(uint32_t) + c->argCap * sizeof(CollArgs);
+  if (stage > c->stageCap) {
+    for (int i = 0; i < 2; ++i) {
+      if (c->hStage[i]) {
+        VCCL_HIPCHECK(hipEventSynchronize(c->stageEvent[i]));
+        VCCL_HIPCHECK(hipHostFree(c->hStage[i]));
+      }
+      VCCL_HIPCHECK(hipHostMalloc(&c->hStage[i], stage, 0));
+    }
+    c->stageCap = stage;
+  }
+  if (stamps > c->stampCap) {
+    size_t cap = stamps < 1024 ? 1024 : stamps * 2;
+    if (c->dStamps) {
+      VCCL_HIPCHECK(hipDeviceSynchronize());
+      VCCL_HIPCHECK(hipFree(c->dStamps));
+    }
+    VCCL_HIPCHECK(hipMalloc((void**)&c->dStamps, cap * sizeof(uint64_t)));
+    c->stampCap = cap;
+  }
+  return vcclSuccess;
+}
+
+int cliqueOccupancy(Clique* c, int nthreads) {
+  int idx = nthreads / 64;
+  if (idx < 1 || idx > 16) return 0;
+  if (c->occupancy[idx] == 0) {
+    int n = 0;
+    if (vcclCollOccupancy(nthreads, &n) != hipSuccess) n = 0;
+    c->occupancy[idx] = n > 0 ? n : -1;
+  }
+  return c->occupancy[idx] > 0 ? c->occupancy[idx] : 0;
+}
+
+}  // namespace vccl

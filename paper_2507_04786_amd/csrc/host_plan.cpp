@@ -1,0 +1,162 @@
+// Planning: algorithm / protocol / channel / chunk choice per collective
+// (Section II-C: after the algorithm and protocol, the tuning model picks how
+// many of the channels built at init to use; Section III-D: LL/LL128 for
+// small messages, Simple for large ones), and the channel partition with
+// its loops and chunks (Section V-C).
+#include <algorithm>
+#include <cmath>
+
+#include "host_internal.h"
+
+namespace vccl {
+
+size_t dtypeBytes(int dtype) { return dtype == vcclBfloat16 ? 2 : 4; }
+
+// Message size in the nccl-tests convention: the larger per-rank buffer.
+uint64_t collSizeBytes(uint8_t coll, size_t count, int dtype, int nranks) {
+  const uint64_t b = (uint64_t)count * dtypeBytes(dtype);
+  if (coll == COLL_ALLGATHER || coll == COLL_REDUCESCATTER) return b * (uint64_t)nranks;
+  return b;
+}
+
+static uint64_t ceilDiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+static uint64_t roundUp(uint64_t a, uint64_t b) { return ceilDiv(a, b) * b; }
+
+static uint64_t unitBytesOf(uint8_t coll, int dtype) {
+  return (coll == COLL_ALLGATHER || coll == COLL_BROADCAST) ? 1 : dtypeBytes(dtype);
+}
+
+static uint64_t unitsOf(uint8_t coll, size_t count, int dtype) {
+  return (coll == COLL_ALLGATHER || coll == COLL_BROADCAST) ? (uint64_t)count * dtypeBytes(dtype) : (uint64_t)count;
+}
+
+// Largest chunk one slot can carry per protocol (slot payload).
+static uint64_t maxChunkBytes(const Clique* c, int proto) {
+  if (proto == PROTO_SIMPLE) return c->host.slotBytes[PROTO_SIMPLE];
+  if (proto == PROTO_LL) return SLOT_BYTES_LL / 2;
+  return (uint64_t)(SLOT_BYTES_LL128 / LL128_LINE) * LL128_DATA;
+}
+
+void channelRange(uint64_t n, int nchannels, uint64_t align, int ch, uint64_t* start, uint64_t* count) {
+  const uint64_t per = n ? roundUp(ceilDiv(n, (uint64_t)nchannels), align) : 0;
+  const uint64_t s = std::min(n, (uint64_t)ch * per);
+  const uint64_t e = std::min(n, (uint64_t)(ch + 1) * per);
+  *start = s;
+  *count = e - s;
+}
+
+vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
+  const int R = c->nranks;
+  const uint64_t S = collSizeBytes(coll.coll, coll.count, coll.dtype, R);
+  auto pick = [&](int api, int env, int dflt) { return api >= 0 ? api : (env >= 0 ? env : dflt); };
+  auto pickPos = [&](long api, long env, long dflt) { return api > 0 ? api : (env > 0 ? env : dflt); };
+
+  // --- algorithm (Tree exists for AllReduce only)
+  int algo = pick(c->apiTune.algo, c->envTune.algo, ALGO_RING);
+  if (algo == ALGO_TREE && coll.coll != COLL_ALLREDUCE) {
+    if (c->apiTune.algo == ALGO_TREE || (c->apiTune.algo < 0 && c->envTune.algo == ALGO_TREE)) {
+      // a forced tree applies to AllReduce; other collectives have only the ring
+      algo = ALGO_RING;
+    }
+  }
+  // --- protocol: small -> LL, large -> Simple
+  int dfltProto = S <= 32 * 1024 ? PROTO_LL : PROTO_SIMPLE;
+  int proto = pick(c->apiTune.proto, c->envTune.proto, dfltProto);
+  // --- channels: keep at least ~256 KiB (Simple) / 16 KiB (LL, LL128) per channel
+  const uint64_t perCh = proto == PROTO_SIMPLE ? 256 * 1024 : 32 * 1024;
+  long dfltC = (long)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)c->maxLanes, S / perCh));
+  int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
+  nch = std::max(1, std::min(nch, c->maxLanes));
+  // --- workgroup size
+  long dfltT = (proto == PROTO_SIMPLE && S >= (4u << 20)) ? 1024 : 256;
+  int nthreads = (int)pickPos(c->apiTune.nthreads, c->envTune.nthreads, dfltT);
+  nthreads = std::max(64, std::min(1024, nthreads / 64 * 64));
+  // co-residency: every workgroup of the launch must be resident at once
+  const int occ = cliqueOccupancy(c, nthreads);
+  if (occ <= 0) return vcclInternalError;
+  const int groupsPerLane = c->xcdMap ? R : R;  // workgroups per lane
+  const int capLanes = std::max(1, (c->numCUs * occ) / groupsPerLane);
+  if (c->xcdMap) {
+    // the XCD map launches 8 * R * ceil(L / 8) workgroups
+    while (nch > 1 && 8 * R * (int)ceilDiv(nch, 8) > c->numCUs * occ) --nch;
+  } else {
+    nch = std::min(nch, capLanes);
+  }
+  // --- chunk
+  const uint64_t maxChunk = maxChunkBytes(c, proto);
+  uint64_t chunk;
+  if (c->apiTune.chunkBytes) chunk = c->apiTune.chunkBytes;
+  else if (c->envTune.chunkBytes) chunk = c->envTune.chunkBytes;
+  else {
+    if (proto == PROTO_SIMPLE) {
+      const uint64_t chBytes = ceilDiv(S, (uint64_t)nch);
+      chunk = roundUp(std::max<uint64_t>(ceilDiv(chBytes, 2 * (uint64_t)R), 16 * 1024), 4096);
+      chunk = std::min<uint64_t>(chunk, 256 * 1024);
+    } else {
+      chunk = maxChunk;
+    }
+  }
+  chunk = std::min(chunk, maxChunk) / 16 * 16;
+  if (chunk < 16) chunk = 16;
+  int direct = pick(c->apiTune.direct, c->envTune.direct, 0);
+  if (proto != PROTO_SIMPLE) direct = 0;
+  plan->algo = algo;
+  plan->proto = proto;
+  plan->nchannels = nch;
+  plan->nthreads = nthreads;
+  plan->direct = direct;
+  plan->chunkBytes = chunk;
+  return vcclSuccess;
+}
+
+void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t argsIndex, uint32_t doneIndex,
+               std::vector<WorkItem>* items) {
+  const uint64_t ub = unitBytesOf(coll.coll, coll.dtype);
+  const uint64_t n = unitsOf(coll.coll, coll.count, coll.dtype);
+  const uint64_t align = 16 / ub;
+  for (int ch = 0; ch < plan.nchannels; ++ch) {
+    WorkItem w{};
+    w.coll = coll.coll;
+    w.algo = (uint8_t)plan.algo;
+    w.proto = (uint8_t)plan.proto;
+    const bool copyOnly = coll.coll == COLL_ALLGATHER || coll.coll == COLL_BROADCAST;
+    w.dtype = copyOnly ? DT_U8 : (uint8_t)(coll.dtype == vcclInt32 ? DT_I32 : coll.dtype == vcclFloat32 ? DT_F32 : DT_BF16);
+    w.op = copyOnly ? OP_COPY : (uint8_t)(coll.op == vcclMax ? OP_MAX : OP_SUM);
+    w.direct = (uint8_t)plan.direct;
+    w.tree = (uint8_t)(ch % 2);
+    w.root = coll.root;
+    w.argsIndex = argsIndex;
+    w.doneIndex = doneIndex;
+    w.unitBytes = (uint32_t)ub;
+    w.elemBytes = (uint32_t)(copyOnly ? 1 : dtypeBytes(coll.dtype));
+    w.count = n;
+    channelRange(n, plan.nchannels, align, ch, &w.chOffset, &w.chCount);
+    w.chunk = plan.chunkBytes / ub;
+    items->push_back(w);
+  }
+  (void)c;
+}
+
+// Rough time (us) of one work item, used to balance lanes in grouped launches.
+double estimateCost(const Clique* c, const WorkItem& w) {
+  const int R = c->nranks;
+  const double bytes = (double)w.chCount * w.unitBytes;
+  const double fifo = w.proto == PROTO_SIMPLE ? 1.0 : (w.proto == PROTO_LL ? 2.0 : 16.0 / 15.0);
+  const double lat = w.proto == PROTO_SIMPLE ? 3.0 : 1.0;
+  double steps, traffic;
+  if (w.coll == COLL_ALLREDUCE) {
+    steps = w.algo == ALGO_TREE ? 2.0 * std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes))
+                                : (2.0 * R - 1) * std::ceil(bytes / std::max<double>(1.0, (double)R * w.chunk * w.unitBytes));
+    traffic = (2.0 * R + 4.0 * fifo * (R - 1)) * bytes / R;
+  } else if (w.coll == COLL_ALLGATHER || w.coll == COLL_REDUCESCATTER) {
+    steps = (double)R * std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes));
+    traffic = (R + 1.0 + 2.0 * fifo * (R - 1)) * bytes;
+  } else {
+    steps = std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes)) + R;
+    traffic = (R + 1.0 + 2.0 * fifo * (R - 1)) * bytes;
+  }
+  const double laneBW = 40e3;  // bytes per us a lane moves, all ranks together (order of magnitude)
+  return steps * lat + traffic / laneBW;
+}
+
+}  // namespace vccl

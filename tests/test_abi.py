@@ -1,0 +1,60 @@
+"""CPU-side checks of the native library: it builds, loads, and exports every
+symbol include/vccl.h declares.  No compute call is made (no GPU here)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vccl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vccl[A-Z]\w*)\s*\(", text)))
+
+
+def test_header_declares_the_paper_api():
+    names = _declared()
+    for must in ("vcclCommInitAll", "vcclCommDestroy", "vcclCommAbort", "vcclAllReduce", "vcclBroadcast",
+                 "vcclReduce", "vcclAllGather", "vcclReduceScatter", "vcclGroupStart", "vcclGroupEnd"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2507_04786_amd as vccl
+    lib = ctypes.CDLL(vccl.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(vccl.EXPORTED) == _declared()
+
+
+def test_error_strings_and_version():
+    import paper_2507_04786_amd as vccl
+    assert vccl.vcclGetVersion() == 1
+    for code in range(8):
+        assert vccl.vcclGetErrorString(code)
+    assert "invalid argument" in vccl.vcclGetErrorString(vccl.vcclInvalidArgument)
+
+
+def test_group_end_without_start_is_invalid_usage():
+    import paper_2507_04786_amd as vccl
+    try:
+        vccl.vcclGroupEnd()
+    except vccl.VcclError as e:
+        assert e.code == vccl.vcclInvalidUsage
+    else:
+        raise AssertionError("expected vcclInvalidUsage")
+    vccl.vcclGroupStart()
+    vccl.vcclGroupEnd()  # an empty group is fine
+
+
+def test_init_rejects_bad_rank_counts():
+    import paper_2507_04786_amd as vccl
+    for n in (0, 1, 17):
+        try:
+            vccl.vcclCommInitAll(n)
+        except vccl.VcclError as e:
+            assert e.code in (vccl.vcclInvalidArgument, vccl.vcclUnhandledHipError)
+        else:
+            raise AssertionError("expected an error")
