@@ -1,0 +1,219 @@
+"""Benchmark: ring AllReduce of 8 virtual ranks on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): ring
+AllReduce, sum, 8 virtual ranks, fp32 N(0,1) synthetic inputs, 64 MiB per
+rank, plan chosen by the library's tuner.  One step = one AllReduce (the
+eight per-rank calls, matched into one launch).  Prints ONE JSON line:
+
+  value       busBW = algBW * 2(R-1)/R, algBW = bytes per rank / step time
+  roofline    HBM-bound kernel: algorithmic bytes of one launch / its average
+              duration (HIP events on the launch stream over the timed
+              region) against the 8 TB/s HBM3E peak
+  protocols   the same AllReduce forced to each protocol (busBW, HBM fraction)
+  cpu_baseline the CPU oracle (numpy schedule simulation) on the same inputs
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib 64]
+                       [--no-cpu] [--no-protocols]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "busBW GB/s & % HBM peak per protocol/size; p50/p99 latency of request stream"
+
+
+def alg_bytes_per_launch(plan: dict, nranks: int, size: int) -> float:
+    """Bytes the ring AllReduce schedule must load and store, FIFO and flag
+    overhead included: [2R + 4f(R-1)] S, f = 1 / 2 / 16/15 for Simple / LL /
+    LL128; (5R - 4) S when the AllGather phase writes straight into the peers'
+    buffers (direct).  Tree AllReduce moves the same bytes as the ring."""
+    R = nranks
+    proto = plan["proto"]
+    if proto == 0 and plan["direct"] and plan["algo"] == 0:
+        return (5 * R - 4) * size
+    f = {0: 1.0, 1: 2.0, 2: 16.0 / 15.0}[proto]
+    return (2 * R + 4 * f * (R - 1)) * size
+
+
+def load_traffic(kernel_key: str):
+    """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
+    from profiles/<key>.traffic.json when it was taken on the current build."""
+    path = os.path.join(ROOT, "profiles", kernel_key + ".traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        lib = os.path.join(ROOT, "paper_2507_04786_amd", "lib", "libvccl.so")
+        import hashlib
+        digest = hashlib.sha256(open(lib, "rb").read()).hexdigest()[:16]
+        if rec.get("lib_sha256_16") != digest:
+            return None
+        return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size-mib", type=int, default=64)
+    ap.add_argument("--nranks", type=int, default=8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-protocols", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="for rocprofv3 counter runs: 3 plain 1 GiB device copies (calibration), "
+                         "then `steps` AllReduces of the workload; prints nothing else")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (virtual ranks live on one device); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2507_04786_amd as vccl
+    import synthetic_inputs as si
+
+    R = args.nranks
+    n = args.size_mib * (1 << 20) // 4
+    S = n * 4
+    torch.cuda.set_device(0)
+    xs = si.rank_inputs(si.WL_RING_AR_SWEEP, R, "float32", n)
+    sends = [torch.from_numpy(x).cuda() for x in xs]
+    recvs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(R)]
+    comms = vccl.vcclCommInitAll(R)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for r in range(R):
+            vccl.vcclAllReduce(sends[r], recvs[r], n, vccl.vcclFloat32, vccl.vcclSum, comms[r], stream)
+
+    def measure(steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        err = vccl.vcclCommGetAsyncError(comms[0])
+        if err != vccl.vcclSuccess:
+            raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)}")
+        return wall / steps, e0.elapsed_time(e1) / 1e3 / steps
+
+    if args.profile_pass:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # scale the counters of the collective kernel to bytes
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        plan = vccl.vcclCommGetLastPlan(comms[0])
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+        print(json.dumps({"profile_pass": True, "plan": plan, "copy_bytes": 2 * (1 << 30)}))
+        return
+
+    # headline: tuner's plan
+    wall_step, ev_step = measure(args.steps, args.warmup)
+    plan = vccl.vcclCommGetLastPlan(comms[0])
+    algbw = S / wall_step / 1e9
+    busbw = algbw * 2 * (R - 1) / R
+    abytes = alg_bytes_per_launch(plan, R, S)
+    achieved = abytes / ev_step / 1e9
+    key = f"collKernel_ring_allreduce_r{R}_{args.size_mib}MiB_fp32"
+    traffic = load_traffic(key)
+
+    protos = {}
+    if not args.no_protocols:
+        for name, code in (("simple", vccl.vcclProtoSimple), ("ll", vccl.vcclProtoLL), ("ll128", vccl.vcclProtoLL128)):
+            vccl.vcclCommSetTuning(comms[0], algo=vccl.vcclAlgoRing, proto=code)
+            w, e = measure(max(3, args.steps // 2), 2)
+            p = vccl.vcclCommGetLastPlan(comms[0])
+            b = alg_bytes_per_launch(p, R, S)
+            protos[name] = {"busbw_gbs": round(S / w / 1e9 * 2 * (R - 1) / R, 2),
+                            "hbm_frac": round(b / e / 1e9 / HBM_PEAK_GBS, 4),
+                            "ms": round(e * 1e3, 4), "nchannels": p["nchannels"], "chunk_bytes": p["chunkBytes"],
+                            "direct": p["direct"]}
+        vccl.vcclCommSetTuning(comms[0])
+
+    # bit-exact spot check of the timed result against the oracle's fold
+    from oracle import folds
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, n, 4096)
+    step()
+    torch.cuda.synchronize()
+    got = recvs[0].cpu().numpy()[idx]
+    want = folds.ring_allreduce(xs, "sum", "float32", plan["nchannels"], plan["chunkBytes"] // 4, idx=idx)
+    exact = bool(np.array_equal(got.view(np.uint32), want.view(np.uint32)))
+
+    cpu = None
+    if not args.no_cpu:
+        from oracle import simulate as sim
+        reps, t_cpu, t0 = 0, 0.0, time.perf_counter()
+        while reps < 2 or (time.perf_counter() - t0 < 10.0 and reps < 50):
+            t1 = time.perf_counter()
+            sim.run("allreduce", xs, dtype="float32", nchannels=plan["nchannels"], chunk_bytes=plan["chunkBytes"])
+            t_cpu += time.perf_counter() - t1
+            reps += 1
+        per = t_cpu / reps
+        cpu = {"value": round(S / per / 1e9 * 2 * (R - 1) / R, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full workload ({R} ranks x {args.size_mib} MiB fp32, same plan), {reps} repetitions, "
+                         f"{t_cpu:.1f} s total, numpy single-threaded"}
+
+    for c in comms:
+        vccl.vcclCommDestroy(c)
+
+    out = {
+        "metric": METRIC,
+        "value": round(busbw, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall_step * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ring AllReduce sum, {R} virtual ranks, fp32 N(0,1), {args.size_mib} MiB per rank",
+                   "nranks": R, "bytes_per_rank": S, "algo": ["ring", "tree"][plan["algo"]],
+                   "proto": ["simple", "ll", "ll128"][plan["proto"]], "nchannels": plan["nchannels"],
+                   "chunk_bytes": plan["chunkBytes"], "nthreads": plan["nthreads"], "direct": plan["direct"]},
+        "algbw_gbs": round(algbw, 2),
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "bit_exact_vs_oracle_sample": exact,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / ev_step / 1e9, 1),
+                     "kernel": "vccl::collKernel", "alg_bytes_per_launch": abytes,
+                     "avg_launch_ms": round(ev_step * 1e3, 4)},
+        "protocols": protos,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

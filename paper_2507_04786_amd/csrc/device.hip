@@ -118,31 +118,48 @@ template <int DT> struct ElemSize { static constexpr int value = (DT == DT_BF16)
 
 // Partial (or misaligned) payload access: element by element, never touching
 // bytes at or beyond `valid`.  Pointers are element-aligned.
-template <int E, int NW>
+template <int E, bool COH>
+__device__ __forceinline__ uint32_t ldElem(const char* p) {
+  if constexpr (COH) {
+    if constexpr (E == 4) return __hip_atomic_load((const uint32_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if constexpr (E == 2) return __hip_atomic_load((const uint16_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return __hip_atomic_load((const uint8_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    if constexpr (E == 4) return *(const uint32_t*)p;
+    else if constexpr (E == 2) return *(const uint16_t*)p;
+    else return *(const uint8_t*)p;
+  }
+}
+template <int E, bool COH>
+__device__ __forceinline__ void stElem(char* p, uint32_t v) {
+  if constexpr (COH) {
+    if constexpr (E == 4) __hip_atomic_store((uint32_t*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else if constexpr (E == 2) __hip_atomic_store((uint16_t*)p, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store((uint8_t*)p, (uint8_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    if constexpr (E == 4) *(uint32_t*)p = v;
+    else if constexpr (E == 2) *(uint16_t*)p = (uint16_t)v;
+    else *(uint8_t*)p = (uint8_t)v;
+  }
+}
+
+// Partial (or misaligned) payload access: element by element, never touching
+// bytes at or beyond `valid`.  Pointers are element-aligned.  COH: device-
+// scope coherent accesses.
+template <int E, int NW, bool COH = false>
 __device__ __forceinline__ void loadPart(const char* p, int valid, uint32_t (&w)[NW]) {
 #pragma unroll
   for (int k = 0; k < NW; ++k) w[k] = 0;
 #pragma unroll
   for (int i = 0; i < NW * 4 / E; ++i) {
-    if (i * E < valid) {
-      uint32_t v;
-      if constexpr (E == 4) v = *(const uint32_t*)(p + i * 4);
-      else if constexpr (E == 2) v = *(const uint16_t*)(p + i * 2);
-      else v = *(const uint8_t*)(p + i);
-      w[(i * E) / 4] |= v << (8 * ((i * E) % 4));
-    }
+    if (i * E < valid) w[(i * E) / 4] |= ldElem<E, COH>(p + i * E) << (8 * ((i * E) % 4));
   }
 }
-template <int E, int NW>
+template <int E, int NW, bool COH = false>
 __device__ __forceinline__ void storePart(char* p, int valid, const uint32_t (&w)[NW]) {
 #pragma unroll
   for (int i = 0; i < NW * 4 / E; ++i) {
-    if (i * E < valid) {
-      uint32_t v = w[(i * E) / 4] >> (8 * ((i * E) % 4));
-      if constexpr (E == 4) *(uint32_t*)(p + i * 4) = v;
-      else if constexpr (E == 2) *(uint16_t*)(p + i * 2) = (uint16_t)v;
-      else *(uint8_t*)(p + i) = (uint8_t)v;
-    }
+    if (i * E < valid) stElem<E, COH>(p + i * E, w[(i * E) / 4] >> (8 * ((i * E) % 4)));
   }
 }
 
@@ -225,7 +242,7 @@ struct PtrList {
 // unroll stride in a scalar offset, and hardware range checks (an access past
 // the stream's end reads zero and writes nothing), so the loop needs no
 // per-vector bounds test.
-template <int DT, int OP, int NIN, int NOUT>
+template <int DT, int OP, int NIN, int NOUT, int CP>
 __device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, const PtrList& out, uint32_t nvec) {
   constexpr int U = 4;
   const uint32_t nb = nvec * 16;
@@ -240,66 +257,70 @@ __device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, c
     u32x4 v0[U], v1[U], v2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v0[u] = __builtin_amdgcn_raw_buffer_load_b128(i0, base, u * stride, 0);
-      if constexpr (NIN > 1) v1[u] = __builtin_amdgcn_raw_buffer_load_b128(i1, base, u * stride, 0);
-      if constexpr (NIN > 2) v2[u] = __builtin_amdgcn_raw_buffer_load_b128(i2, base, u * stride, 0);
+      v0[u] = __builtin_amdgcn_raw_buffer_load_b128(i0, base, u * stride, CP);
+      if constexpr (NIN > 1) v1[u] = __builtin_amdgcn_raw_buffer_load_b128(i1, base, u * stride, CP);
+      if constexpr (NIN > 2) v2[u] = __builtin_amdgcn_raw_buffer_load_b128(i2, base, u * stride, CP);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       u32x4 acc = v0[u];
       if constexpr (NIN > 1) acc = redVec4<DT, OP>(acc, v1[u]);
       if constexpr (NIN > 2) acc = redVec4<DT, OP>(acc, v2[u]);
-      __builtin_amdgcn_raw_buffer_store_b128(acc, o0, base, u * stride, 0);
-      if constexpr (NOUT > 1) __builtin_amdgcn_raw_buffer_store_b128(acc, o1, base, u * stride, 0);
-      if constexpr (NOUT > 2) __builtin_amdgcn_raw_buffer_store_b128(acc, o2, base, u * stride, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(acc, o0, base, u * stride, CP);
+      if constexpr (NOUT > 1) __builtin_amdgcn_raw_buffer_store_b128(acc, o1, base, u * stride, CP);
+      if constexpr (NOUT > 2) __builtin_amdgcn_raw_buffer_store_b128(acc, o2, base, u * stride, CP);
     }
   }
 }
 
 // Same operation on any element-aligned pointers, 16 bytes (or the tail) per
 // lane through element-wise accesses.  Used for misaligned buffers and tails.
-template <int DT, int OP, int NIN, int NOUT>
+template <int DT, int OP, int NIN, int NOUT, bool COH>
 __device__ __forceinline__ void reduceCopyPart(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t begin,
                                                uint64_t nbytes) {
   constexpr int E = ElemSize<DT>::value;
   for (uint64_t off = begin + (uint64_t)c.tid * 16; off < nbytes; off += (uint64_t)c.nthreads * 16) {
     const int valid = (int)((nbytes - off) < 16 ? (nbytes - off) : 16);
     uint32_t acc[4], w[4];
-    loadPart<E, 4>(in.p0 + off, valid, acc);
+    loadPart<E, 4, COH>(in.p0 + off, valid, acc);
     if constexpr (NIN > 1) {
-      loadPart<E, 4>(in.p1 + off, valid, w);
+      loadPart<E, 4, COH>(in.p1 + off, valid, w);
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = redWord<DT, OP>(acc[q], w[q]);
     }
     if constexpr (NIN > 2) {
-      loadPart<E, 4>(in.p2 + off, valid, w);
+      loadPart<E, 4, COH>(in.p2 + off, valid, w);
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = redWord<DT, OP>(acc[q], w[q]);
     }
-    storePart<E, 4>((char*)out.p0 + off, valid, acc);
-    if constexpr (NOUT > 1) storePart<E, 4>((char*)out.p1 + off, valid, acc);
-    if constexpr (NOUT > 2) storePart<E, 4>((char*)out.p2 + off, valid, acc);
+    storePart<E, 4, COH>((char*)out.p0 + off, valid, acc);
+    if constexpr (NOUT > 1) storePart<E, 4, COH>((char*)out.p1 + off, valid, acc);
+    if constexpr (NOUT > 2) storePart<E, 4, COH>((char*)out.p2 + off, valid, acc);
   }
 }
 
-template <int DT, int OP, int NIN, int NOUT>
+// MODE: SIMPLE_FENCE (plain accesses) or SIMPLE_COHERENT (device-scope
+// coherent accesses on every stream of the step).
+template <int DT, int OP, int NIN, int NOUT, int MODE>
 __device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
+  constexpr int CP = MODE == SIMPLE_COHERENT ? 16 : 0;  // sc1
+  constexpr bool COH = MODE == SIMPLE_COHERENT;
   const uintptr_t bits = (uintptr_t)in.p0 | (uintptr_t)in.p1 | (uintptr_t)in.p2 | (uintptr_t)out.p0 |
                          (uintptr_t)out.p1 | (uintptr_t)out.p2;
   if ((bits & 15) == 0) {
     const uint32_t nvec = (uint32_t)(nbytes / 16);
-    reduceCopyVec<DT, OP, NIN, NOUT>(c, in, out, nvec);
-    if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT>(c, in, out, (uint64_t)nvec * 16, nbytes);
+    reduceCopyVec<DT, OP, NIN, NOUT, CP>(c, in, out, nvec);
+    if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT, COH>(c, in, out, (uint64_t)nvec * 16, nbytes);
   } else {
-    reduceCopyPart<DT, OP, NIN, NOUT>(c, in, out, 0, nbytes);
+    reduceCopyPart<DT, OP, NIN, NOUT, COH>(c, in, out, 0, nbytes);
   }
 }
 
-template <int DT, int OP>
+template <int DT, int OP, int MODE>
 __device__ void reduceCopyN(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
   if (nbytes == 0 || in.n == 0 || out.n == 0) return;
 #define VCCL_RC(I, O) \
-  if (in.n == I && out.n == O) { reduceCopy<DT, OP, I, O>(c, in, out, nbytes); return; }
+  if (in.n == I && out.n == O) { reduceCopy<DT, OP, I, O, MODE>(c, in, out, nbytes); return; }
   VCCL_RC(1, 1) VCCL_RC(1, 2) VCCL_RC(1, 3) VCCL_RC(2, 1) VCCL_RC(2, 2) VCCL_RC(2, 3) VCCL_RC(3, 1) VCCL_RC(3, 2)
   VCCL_RC(3, 3)
 #undef VCCL_RC
@@ -326,6 +347,7 @@ struct StepArgs {
 
 template <int DT, int OP>
 __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
+  const uint32_t coherent = c.comm->simpleMode;
   if (c.tid == 0) {
     bool ok = true;
 #pragma unroll
@@ -334,7 +356,7 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
       if (ok && (a.rmask & (1 << i))) ok = waitCounter(c, r[i].tail, r[i].step + 1);
-    if (a.rmask) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (a.rmask && coherent == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!ok) *c.sAbort = 1;
   }
   __syncthreads();
@@ -354,13 +376,14 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 #pragma unroll
   for (int j = 0; j < 3; ++j)
     if (a.smask & (1 << j)) out.add(a.sendDirect[j] ? a.sendDirect[j] : s[j].fifo + (s[j].step % NSLOTS) * slotB);
-  reduceCopyN<DT, OP>(c, in, out, a.nbytes);
+  if (coherent) reduceCopyN<DT, OP, SIMPLE_COHERENT>(c, in, out, a.nbytes);
+  else reduceCopyN<DT, OP, SIMPLE_FENCE>(c, in, out, a.nbytes);
 
   drainVmem();
   __syncthreads();
   if (c.tid == 0) {
     if (a.smask) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (!coherent) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 #pragma unroll
       for (int j = 0; j < 3; ++j)
         if (a.smask & (1 << j)) stAgent(s[j].tail, s[j].step + 1);
@@ -602,6 +625,12 @@ __device__ __forceinline__ uint64_t connId(const Ctx& c, int receiver, int kind)
   return ((uint64_t)c.lane * c.nranks + receiver) * NCONN + kind;
 }
 
+__device__ __forceinline__ char* fifoOf(const Ctx& c, int proto, int receiver, int kind, uint64_t fifoBytes) {
+  const uint64_t lr = (uint64_t)c.lane * c.nranks + receiver;
+  if (kind == 0) return c.comm->fifo[proto] + lr * fifoBytes;
+  return c.comm->treeFifo[proto] + (lr * (NCONN - 1) + (kind - 1)) * fifoBytes;
+}
+
 // Thread 0 reads the step counters (a receiver's own head, a sender's own
 // tail) and all threads pick them up from LDS.
 __device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, Conn* s, const int* speer,
@@ -611,13 +640,13 @@ __device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, C
   for (int i = 0; i < 3; ++i) {
     if (rkind[i] >= 0) {
       uint64_t id = connId(c, c.rank, rkind[i]);
-      r[i].fifo = c.comm->fifo[proto] + id * fifoBytes;
+      r[i].fifo = fifoOf(c, proto, c.rank, rkind[i], fifoBytes);
       r[i].tail = c.comm->ctr + id * CTR_RECORD_U64;
       r[i].head = r[i].tail + CTR_HEAD_U64;
     }
     if (speer[i] >= 0) {
       uint64_t id = connId(c, speer[i], skind[i]);
-      s[i].fifo = c.comm->fifo[proto] + id * fifoBytes;
+      s[i].fifo = fifoOf(c, proto, speer[i], skind[i], fifoBytes);
       s[i].tail = c.comm->ctr + id * CTR_RECORD_U64;
       s[i].head = s[i].tail + CTR_HEAD_U64;
     }

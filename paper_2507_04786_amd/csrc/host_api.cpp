@@ -80,6 +80,10 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   for (size_t g = 0; g < colls.size(); ++g) {
     vcclResult_t r = planColl(c, colls[g], &plans[g]);
     if (r != vcclSuccess) return r;
+    if (plans[g].algo == ALGO_TREE) {
+      r = cliqueEnsureTreeFifos(c);
+      if (r != vcclSuccess) return r;
+    }
   }
   StreamSet ss;
   for (const auto& x : colls)
@@ -456,7 +460,7 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
     return vcclInvalidArgument;
   const uint64_t fifoBytes = (uint64_t)NSLOTS * c->host.slotBytes[proto];
   if (offset + bytes > fifoBytes) return vcclInvalidArgument;
-  const uint64_t id = ((uint64_t)channel * c->nranks + rank) * NCONN + 0;
+  const uint64_t id = (uint64_t)channel * c->nranks + rank;
   VCCL_HIPCHECK(hipSetDevice(c->device));
   VCCL_HIPCHECK(hipDeviceSynchronize());
   VCCL_HIPCHECK(hipMemcpy(dst, c->fifo[proto] + id * fifoBytes + offset, bytes, hipMemcpyDeviceToHost));

@@ -97,7 +97,7 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   Clique* c = new Clique();
   c->nranks = nranks;
   c->device = device;
-  c->maxLanes = (int)envLong("VCCL_MAX_CHANNELS", 16);
+  c->maxLanes = (int)envLong("VCCL_MAX_CHANNELS", 32);
   if (c->maxLanes < 1) c->maxLanes = 1;
   if (c->maxLanes > MAX_LANES) c->maxLanes = MAX_LANES;
   c->pending.resize(nranks);
@@ -120,7 +120,7 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   const uint64_t slot[3] = {(uint64_t)envLong("VCCL_SIMPLE_SLOT_BYTES", SLOT_BYTES_SIMPLE), SLOT_BYTES_LL,
                             SLOT_BYTES_LL128};
   for (int p = 0; p < 3; ++p) {
-    const uint64_t bytes = nconn * NSLOTS * slot[p];
+    const uint64_t bytes = (uint64_t)c->maxLanes * nranks * NSLOTS * slot[p];  // ring connections
     e = hipMalloc((void**)&c->fifo[p], bytes);
     if (e != hipSuccess) return fail(e, "hipMalloc(fifo)");
     if (p != PROTO_SIMPLE) {
@@ -147,6 +147,7 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   const double timeoutUs = (double)envLong("VCCL_TIMEOUT_US", 5000000);
   c->host.timeoutTicks = (uint64_t)(timeoutUs * c->ticksPerUs);
   c->host.deadMask = 0;
+  c->host.simpleMode = envStr("VCCL_SIMPLE_SYNC") == "fence" ? SIMPLE_FENCE : SIMPLE_COHERENT;
   c->host.ctr = c->ctr;
   c->host.abortFlag = c->hAbort;
   c->host.errorWord = c->hError;
@@ -182,7 +183,9 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   c->envTune.nthreads = (int)envLong("VCCL_NTHREADS", 0);
   c->envTune.chunkBytes = (uint64_t)envLong("VCCL_CHUNK_BYTES", 0);
   c->envTune.direct = (int)envLong("VCCL_DIRECT", -1);
-  c->cooperative = envStr("VCCL_LAUNCH") != "plain";
+  // plain launches by default: the planner keeps every launch within what the
+  // device holds at once (grid <= CUs * occupancy), and every wait is bounded
+  c->cooperative = envStr("VCCL_LAUNCH") == "cooperative";
   c->xcdMap = (int)envLong("VCCL_XCD_MAP", 1);
   *out = c;
   return vcclSuccess;
@@ -192,8 +195,10 @@ void cliqueFree(Clique* c) {
   if (!c) return;
   hipSetDevice(c->device);
   hipDeviceSynchronize();
-  for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < 3; ++p) {
     if (c->fifo[p]) hipFree(c->fifo[p]);
+    if (c->treeFifo[p]) hipFree(c->treeFifo[p]);
+  }
   if (c->ctr) hipFree(c->ctr);
   if (c->dcomm) hipFree(c->dcomm);
   if (c->dItems) hipFree(c->dItems);
@@ -211,6 +216,22 @@ void cliqueFree(Clique* c) {
   if (c->hError) hipHostFree(c->hError);
   for (auto* h : c->handles) delete h;
   delete c;
+}
+
+// Tree connections are allocated on the first tree launch (they are 6 of the
+// 7 connections of every lane and rank and only tree AllReduce uses them).
+vcclResult_t cliqueEnsureTreeFifos(Clique* c) {
+  if (c->treeFifo[0]) return vcclSuccess;
+  VCCL_HIPCHECK(hipDeviceSynchronize());
+  for (int p = 0; p < 3; ++p) {
+    const uint64_t bytes = (uint64_t)c->maxLanes * c->nranks * (NCONN - 1) * NSLOTS * c->host.slotBytes[p];
+    VCCL_HIPCHECK(hipMalloc((void**)&c->treeFifo[p], bytes));
+    if (p != PROTO_SIMPLE) VCCL_HIPCHECK(hipMemset(c->treeFifo[p], 0, bytes));
+    c->host.treeFifo[p] = c->treeFifo[p];
+  }
+  VCCL_HIPCHECK(hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice));
+  VCCL_HIPCHECK(hipDeviceSynchronize());
+  return vcclSuccess;
 }
 
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps) {

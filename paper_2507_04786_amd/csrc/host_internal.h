@@ -61,6 +61,7 @@ struct Clique {
   DevComm host{};             // host copy of the device descriptor
   DevComm* dcomm = nullptr;   // device copy
   char* fifo[3] = {nullptr, nullptr, nullptr};
+  char* treeFifo[3] = {nullptr, nullptr, nullptr};
   uint64_t* ctr = nullptr;
   uint32_t* hAbort = nullptr; // pinned
   uint32_t* hError = nullptr; // pinned
@@ -97,6 +98,7 @@ int rankOf(vcclComm_t comm);
 // host_comm.cpp
 vcclResult_t cliqueCreate(int nranks, int device, Clique** out);
 void cliqueFree(Clique* c);
+vcclResult_t cliqueEnsureTreeFifos(Clique* c);
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps);
 int cliqueOccupancy(Clique* c, int nthreads);
 void buildTrees(int nranks, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2],

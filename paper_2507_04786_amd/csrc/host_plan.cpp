@@ -59,28 +59,32 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
       algo = ALGO_RING;
     }
   }
-  // --- protocol: small -> LL, large -> Simple
-  int dfltProto = S <= 32 * 1024 ? PROTO_LL : PROTO_SIMPLE;
+  // --- protocol: small -> LL, large -> Simple (measured crossover near 1 MiB
+  // per rank for 8 ranks)
+  int dfltProto = S <= (1u << 20) ? PROTO_LL : PROTO_SIMPLE;
   int proto = pick(c->apiTune.proto, c->envTune.proto, dfltProto);
-  // --- channels: keep at least ~256 KiB (Simple) / 16 KiB (LL, LL128) per channel
-  const uint64_t perCh = proto == PROTO_SIMPLE ? 256 * 1024 : 32 * 1024;
-  long dfltC = (long)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)c->maxLanes, S / perCh));
+  // tree AllReduce: 2 log2(R) hops instead of 2R - 1, so it wins on latency
+  if (c->apiTune.algo < 0 && c->envTune.algo < 0 && coll.coll == COLL_ALLREDUCE && R >= 4 && S <= 64 * 1024)
+    algo = ALGO_TREE;
+  // --- channels: one workgroup per CU at most (R * C <= 256), and enough
+  // bytes per channel to amortise the per-step synchronisation
+  const uint64_t perCh = proto == PROTO_SIMPLE ? 512 * 1024 : 16 * 1024;
+  const int laneCap = std::max(1, std::min(c->maxLanes, c->numCUs / R));
+  long dfltC = (long)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)laneCap, S / perCh));
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));
   // --- workgroup size
-  long dfltT = (proto == PROTO_SIMPLE && S >= (4u << 20)) ? 1024 : 256;
+  long dfltT = (proto == PROTO_SIMPLE || S >= (256u << 10)) ? 512 : 256;
   int nthreads = (int)pickPos(c->apiTune.nthreads, c->envTune.nthreads, dfltT);
   nthreads = std::max(64, std::min(1024, nthreads / 64 * 64));
   // co-residency: every workgroup of the launch must be resident at once
   const int occ = cliqueOccupancy(c, nthreads);
   if (occ <= 0) return vcclInternalError;
-  const int groupsPerLane = c->xcdMap ? R : R;  // workgroups per lane
-  const int capLanes = std::max(1, (c->numCUs * occ) / groupsPerLane);
   if (c->xcdMap) {
     // the XCD map launches 8 * R * ceil(L / 8) workgroups
     while (nch > 1 && 8 * R * (int)ceilDiv(nch, 8) > c->numCUs * occ) --nch;
   } else {
-    nch = std::min(nch, capLanes);
+    nch = std::min(nch, std::max(1, (c->numCUs * occ) / R));
   }
   // --- chunk
   const uint64_t maxChunk = maxChunkBytes(c, proto);
@@ -89,16 +93,18 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   else if (c->envTune.chunkBytes) chunk = c->envTune.chunkBytes;
   else {
     if (proto == PROTO_SIMPLE) {
+      // a ring loop covers R chunks: take the largest chunk that still gives
+      // every channel at least one full loop
       const uint64_t chBytes = ceilDiv(S, (uint64_t)nch);
-      chunk = roundUp(std::max<uint64_t>(ceilDiv(chBytes, 2 * (uint64_t)R), 16 * 1024), 4096);
-      chunk = std::min<uint64_t>(chunk, 256 * 1024);
+      chunk = roundUp(std::max<uint64_t>(ceilDiv(chBytes, (uint64_t)R), 16 * 1024), 4096);
+      chunk = std::min<uint64_t>(chunk, maxChunk);
     } else {
       chunk = maxChunk;
     }
   }
   chunk = std::min(chunk, maxChunk) / 16 * 16;
   if (chunk < 16) chunk = 16;
-  int direct = pick(c->apiTune.direct, c->envTune.direct, 0);
+  int direct = pick(c->apiTune.direct, c->envTune.direct, 1);
   if (proto != PROTO_SIMPLE) direct = 0;
   plan->algo = algo;
   plan->proto = proto;

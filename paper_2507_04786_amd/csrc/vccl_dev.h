@@ -1,8 +1,11 @@
 // Structures shared by the host runtime and the gfx950 kernels.
 //
 // Memory layout in HBM (one communicator set, "clique"):
-//   * FIFOs: for every protocol p, one contiguous region of
-//       maxLanes * nranks * NCONN connections * NSLOTS slots * slotBytes[p].
+//   * FIFOs: for every protocol p, one region for the ring connections,
+//       maxLanes * nranks connections of NSLOTS slots * slotBytes[p] each
+//       (index lane * nranks + receivingRank), and one for the tree
+//       connections (6 per lane and rank, index (lane * nranks + rank) * 6 +
+//       kind - 1), allocated on the first tree launch.
 //     Connection id = (lane * nranks + receivingRank) * NCONN + kind, where kind
 //       0      ring: from the ring predecessor
 //       1, 2   tree 0: upward from the receiver's first / second child
@@ -37,6 +40,15 @@ constexpr uint32_t LL128_LINE = 128, LL128_DATA = 120;
 constexpr uint32_t CTR_RECORD_U64 = 32;  // 256 B per connection
 constexpr uint32_t CTR_HEAD_U64 = 16;    // head at +128 B
 
+// Simple-protocol synchronisation modes.
+//  SIMPLE_FENCE: plain stores, device-scope release fence (L2 write-back)
+//    before the tail store; device-scope acquire (L2 invalidate) after it.
+//  SIMPLE_COHERENT: the chunk itself is stored and loaded with device-scope
+//    coherent accesses (sc1, as relaxed device-scope atomics are), so a drain
+//    of the stores before the tail store orders them and no cache-wide
+//    write-back or invalidate is needed.
+constexpr uint32_t SIMPLE_FENCE = 0, SIMPLE_COHERENT = 1;
+
 // device-side error codes (bit flags in the error word)
 constexpr uint32_t ERR_TIMEOUT = 1u, ERR_ABORT = 2u;
 
@@ -45,8 +57,9 @@ struct DevComm {
   int32_t maxLanes;
   uint64_t timeoutTicks;        // device wall-clock ticks a single wait may take
   uint32_t deadMask;            // test hook: ranks whose workgroups do nothing
-  uint32_t pad0;
-  char* fifo[3];                // per protocol
+  uint32_t simpleMode;          // Simple protocol synchronisation, SIMPLE_* below
+  char* fifo[3];                // ring connections, per protocol
+  char* treeFifo[3];            // tree connections, per protocol (null until first used)
   uint64_t slotBytes[3];
   uint64_t* ctr;                // counters
   uint32_t* abortFlag;          // host-pinned, written by the host
