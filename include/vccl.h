@@ -170,6 +170,7 @@ typedef struct {
   int algo, proto, nchannels, nthreads, direct, nlanes, nitems, ncolls;
   size_t chunkBytes;
   int grid;           /* workgroups launched */
+  int scope;          /* 0: peers anywhere on the device, 1: each channel on one XCD */
 } vcclPlanInfo_t;
 vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info);
 
@@ -231,6 +232,18 @@ vcclResult_t vcclServeSubmit(vcclServer_t server, const vcclRequest_t* req, uint
  * reports whether `id` has completed; t_done_ns receives the host
  * monotonic time (ns) at which completion was observed. */
 vcclResult_t vcclServeTest(vcclServer_t server, uint64_t id, int* done, vcclResult_t* status, uint64_t* t_done_ns);
+/* Native request loop: submits reqs[i] when arrival_ns[i] nanoseconds have
+ * passed since the call began (arrival_ns non-decreasing), keeps making
+ * progress, and returns when all n requests completed.  latency_ns[i]
+ * receives completion time - arrival time; statuses (may be NULL) the
+ * per-request result.  Host arrays of n entries, caller-owned. */
+vcclResult_t vcclServeReplay(vcclServer_t server, const vcclRequest_t* reqs, const uint64_t* arrival_ns, int n,
+                             uint64_t* latency_ns, vcclResult_t* statuses);
+/* Monitoring: for each of the first maxEntries (lane, rank) pairs, 5 words
+ * into out[]: requests posted to the lane (host), the last posted count the
+ * device observed, entries it picked up, entries it completed, and its poll
+ * iteration count.  Reads host memory only. */
+vcclResult_t vcclServeDebugState(vcclServer_t server, uint64_t* out, int maxEntries);
 /* Drains every request, stops the persistent kernel and frees. */
 vcclResult_t vcclServeDestroy(vcclServer_t server);
 

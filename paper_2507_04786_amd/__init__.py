@@ -8,7 +8,7 @@ carrying the code; functions that return values through pointers in C return
 them here.
 
 The native library is paper_2507_04786_amd/lib/libvccl.so, built in-tree by
-``paper_2507_04786_amd.build.build()``.  Importing this module without it
+``python paper_2507_04786_amd/build.py`` (or ``__graft_entry__.build()``).  Importing this module without it
 raises ImportError: there is no fallback implementation.
 """
 from __future__ import annotations
@@ -58,7 +58,7 @@ class vcclTuning_t(C.Structure):
 class vcclPlanInfo_t(C.Structure):
     _fields_ = [("algo", C.c_int), ("proto", C.c_int), ("nchannels", C.c_int), ("nthreads", C.c_int),
                 ("direct", C.c_int), ("nlanes", C.c_int), ("nitems", C.c_int), ("ncolls", C.c_int),
-                ("chunkBytes", C.c_size_t), ("grid", C.c_int)]
+                ("chunkBytes", C.c_size_t), ("grid", C.c_int), ("scope", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,7 +72,14 @@ class vcclRequest_t(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"vccl native library not built: {LIB_PATH} is missing "
-                          "(run paper_2507_04786_amd.build.build())")
+                          "(run python paper_2507_04786_amd/build.py)")
+    try:
+        # torch ships its own HIP runtime under the same soname; loading it
+        # first lets the library bind to that one copy (a second runtime in
+        # the process would keep torch from initialising the device)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P, I, U64, SZ, VP = C.c_void_p, C.c_int, C.c_uint64, C.c_size_t, C.c_void_p
     sig = {
@@ -103,6 +110,8 @@ def _load():
         "vcclServeSubmit": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64)]),
         "vcclServeTest": (I, [P, U64, C.POINTER(I), C.POINTER(I), C.POINTER(U64)]),
         "vcclServeDestroy": (I, [P]),
+        "vcclServeReplay": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64), I, C.POINTER(U64), C.POINTER(I)]),
+        "vcclServeDebugState": (I, [P, C.POINTER(U64), I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -117,7 +126,7 @@ EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy v
             "vcclAllGather vcclReduceScatter vcclGroupStart vcclGroupEnd vcclCommSetTuning vcclCommGetLastPlan "
             "vcclCommGetLastTimestamps vcclCommSetTimeout vcclCommDebugSetDeadRanks vcclCommDebugReadFifo "
             "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
-            "vcclServeDestroy").split()
+            "vcclServeDestroy vcclServeReplay vcclServeDebugState").split()
 
 
 def lib():
@@ -275,13 +284,18 @@ def vcclServeCreate(comms, budgetBytes: int, lanes: int):
     return out
 
 
-def vcclServeSubmit(server, coll, datatype, op, root, count, sends, recvs) -> int:
+def make_request(coll, datatype, op, root, count, sends, recvs) -> vcclRequest_t:
     req = vcclRequest_t()
     req.coll, req.datatype, req.op, req.root, req.count = int(coll), int(datatype), int(op), int(root), int(count)
     for i, s in enumerate(sends):
         req.send[i] = _ptr(s)
     for i, r in enumerate(recvs):
         req.recv[i] = _ptr(r)
+    return req
+
+
+def vcclServeSubmit(server, coll, datatype, op, root, count, sends, recvs) -> int:
+    req = make_request(coll, datatype, op, root, count, sends, recvs)
     rid = C.c_uint64()
     _check(_lib.vcclServeSubmit(server, C.byref(req), C.byref(rid)), "vcclServeSubmit")
     return rid.value
@@ -291,6 +305,24 @@ def vcclServeTest(server, rid: int):
     done, status, t = C.c_int(), C.c_int(), C.c_uint64()
     _check(_lib.vcclServeTest(server, int(rid), C.byref(done), C.byref(status), C.byref(t)), "vcclServeTest")
     return bool(done.value), status.value, t.value
+
+
+def vcclServeReplay(server, requests, arrival_ns):
+    """requests: list of vcclRequest_t; arrival_ns: offsets from the start.
+    Returns (latency_ns list, status list)."""
+    n = len(requests)
+    arr = (vcclRequest_t * n)(*requests)
+    at = (C.c_uint64 * n)(*[int(x) for x in arrival_ns])
+    lat = (C.c_uint64 * n)()
+    st = (C.c_int * n)()
+    _check(_lib.vcclServeReplay(server, arr, at, n, lat, st), "vcclServeReplay")
+    return list(lat), list(st)
+
+
+def vcclServeDebugState(server, entries: int):
+    arr = (C.c_uint64 * (5 * entries))()
+    _check(_lib.vcclServeDebugState(server, arr, int(entries)), "vcclServeDebugState")
+    return [list(arr[5 * k:5 * k + 5]) for k in range(entries)]
 
 
 def vcclServeDestroy(server):

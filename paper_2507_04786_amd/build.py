@@ -1,6 +1,6 @@
 """Builds the native library (HIP for gfx950 + host C++) in-tree.
 
-    python -m paper_2507_04786_amd.build        # or build() from Python
+    python paper_2507_04786_amd/build.py        # (run by path, not as a module)
 
 Produces paper_2507_04786_amd/lib/libvccl.so.  Every source is compiled by
 hipcc for gfx950 only; objects are cached per source under

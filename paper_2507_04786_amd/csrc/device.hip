@@ -55,13 +55,49 @@ __device__ __forceinline__ uint64_t nowTicks() { return __builtin_amdgcn_s_memre
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t makeRsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-// 16-byte load / store with device-scope coherence (sc1): bypasses the
-// non-coherent per-CU cache so a line written by another workgroup is seen.
-__device__ __forceinline__ u32x4 ldLine16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 16);
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Scope of the bulk data traffic of the Simple protocol (DevComm::scope).
+//  SCOPE_DEVICE: peers may sit on any XCD: chunks are stored and loaded with
+//    device-scope coherent accesses (sc1, as relaxed device-scope atomics do),
+//    so draining the stores before the tail store is the whole release and no
+//    cache-wide write-back or invalidate is needed.
+//  SCOPE_XCD: every workgroup of a lane runs on the same XCD (roles are
+//    claimed per XCD at kernel start), so that XCD's L2 is the point of
+//    coherence for the chunk: the producer stores through the write-through CU
+//    cache into L2 and drains; the consumer, once it has seen the tail,
+//    invalidates its CU cache (buffer_inv sc0 -- the acquire of the workgroup
+//    scope in threadgroup-split mode, where waves share only L2) and loads
+//    plainly, hitting L2 while the chunk is still there.
+// Flags, counters and the LL / LL128 lines always use device scope.
+template <int SC> struct Aux { static constexpr int value = 16; };
+
+template <int SC>
+__device__ __forceinline__ uint64_t ldCtr(const uint64_t* p) { return ldAgent(p); }
+template <int SC>
+__device__ __forceinline__ void stCtr(uint64_t* p, uint64_t v) { stAgent(p, v); }
+// After a tail was observed, before the chunk it announces is read.
+template <int SC>
+__device__ __forceinline__ void acquireData() {
+  if constexpr (SC == SCOPE_XCD) asm volatile("buffer_inv sc0" ::: "memory");
 }
+// 8-byte LL unit and 16-byte LL128 line access (one instruction each).
+template <int SC>
+__device__ __forceinline__ uint64_t ldUnit(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, Aux<SC>::value);
+  return (uint64_t)v.x | ((uint64_t)v.y << 32);
+}
+template <int SC>
+__device__ __forceinline__ void stUnit(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t v) {
+  __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)v, (uint32_t)(v >> 32)}, r, off, 0, Aux<SC>::value);
+}
+template <int SC>
+__device__ __forceinline__ u32x4 ldLine16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, Aux<SC>::value);
+}
+template <int SC>
 __device__ __forceinline__ void stLine16(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, 16);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, Aux<SC>::value);
 }
 
 // ------------------------------------------------------------------ element operators
@@ -185,13 +221,14 @@ __device__ __forceinline__ uint64_t creditTarget(uint64_t step) { return step + 
 
 // Bounded wait for *ctr >= target, one lane.  Returns false (and records the
 // error) on timeout or abort.
+template <int SC>
 __device__ __noinline__ bool waitCounter(const Ctx& c, const uint64_t* ctr, uint64_t target) {
-  if (ldAgent(ctr) >= target) return true;
+  if (ldCtr<SC>(ctr) >= target) return true;
   uint64_t t0 = nowTicks();
   uint32_t it = 0;
   for (;;) {
     __builtin_amdgcn_s_sleep(1);
-    if (ldAgent(ctr) >= target) return true;
+    if (ldCtr<SC>(ctr) >= target) return true;
     if ((++it & 63u) == 0) {
       if (ldSystem32(c.comm->abortFlag)) { orSystem32(c.comm->errorWord, ERR_ABORT); return false; }
       if (nowTicks() - t0 > c.comm->timeoutTicks) { orSystem32(c.comm->errorWord, ERR_TIMEOUT); return false; }
@@ -299,12 +336,12 @@ __device__ __forceinline__ void reduceCopyPart(const Ctx& c, const PtrList& in, 
   }
 }
 
-// MODE: SIMPLE_FENCE (plain accesses) or SIMPLE_COHERENT (device-scope
-// coherent accesses on every stream of the step).
-template <int DT, int OP, int NIN, int NOUT, int MODE>
+// SC: SCOPE_DEVICE -> device-scope coherent accesses on every stream of the
+// step; SCOPE_XCD -> plain accesses (the consumer invalidated its CU cache).
+template <int DT, int OP, int NIN, int NOUT, int SC>
 __device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
-  constexpr int CP = MODE == SIMPLE_COHERENT ? 16 : 0;  // sc1
-  constexpr bool COH = MODE == SIMPLE_COHERENT;
+  constexpr int CP = SC == SCOPE_DEVICE ? 16 : 0;  // sc1
+  constexpr bool COH = SC == SCOPE_DEVICE;
   const uintptr_t bits = (uintptr_t)in.p0 | (uintptr_t)in.p1 | (uintptr_t)in.p2 | (uintptr_t)out.p0 |
                          (uintptr_t)out.p1 | (uintptr_t)out.p2;
   if ((bits & 15) == 0) {
@@ -316,11 +353,11 @@ __device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const P
   }
 }
 
-template <int DT, int OP, int MODE>
+template <int DT, int OP, int SC>
 __device__ void reduceCopyN(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
   if (nbytes == 0 || in.n == 0 || out.n == 0) return;
 #define VCCL_RC(I, O) \
-  if (in.n == I && out.n == O) { reduceCopy<DT, OP, I, O, MODE>(c, in, out, nbytes); return; }
+  if (in.n == I && out.n == O) { reduceCopy<DT, OP, I, O, SC>(c, in, out, nbytes); return; }
   VCCL_RC(1, 1) VCCL_RC(1, 2) VCCL_RC(1, 3) VCCL_RC(2, 1) VCCL_RC(2, 2) VCCL_RC(2, 3) VCCL_RC(3, 1) VCCL_RC(3, 2)
   VCCL_RC(3, 3)
 #undef VCCL_RC
@@ -345,18 +382,17 @@ struct StepArgs {
   bool recvDirect;
 };
 
-template <int DT, int OP>
+template <int SC, int DT, int OP>
 __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
-  const uint32_t coherent = c.comm->simpleMode;
   if (c.tid == 0) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      if (ok && (a.smask & (1 << j))) ok = waitCounter(c, s[j].head, creditTarget(s[j].step));
+      if (ok && (a.smask & (1 << j))) ok = waitCounter<SC>(c, s[j].head, creditTarget(s[j].step));
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      if (ok && (a.rmask & (1 << i))) ok = waitCounter(c, r[i].tail, r[i].step + 1);
-    if (a.rmask && coherent == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (ok && (a.rmask & (1 << i))) ok = waitCounter<SC>(c, r[i].tail, r[i].step + 1);
+    if (a.rmask) acquireData<SC>();
     if (!ok) *c.sAbort = 1;
   }
   __syncthreads();
@@ -376,21 +412,19 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 #pragma unroll
   for (int j = 0; j < 3; ++j)
     if (a.smask & (1 << j)) out.add(a.sendDirect[j] ? a.sendDirect[j] : s[j].fifo + (s[j].step % NSLOTS) * slotB);
-  if (coherent) reduceCopyN<DT, OP, SIMPLE_COHERENT>(c, in, out, a.nbytes);
-  else reduceCopyN<DT, OP, SIMPLE_FENCE>(c, in, out, a.nbytes);
+  reduceCopyN<DT, OP, SC>(c, in, out, a.nbytes);
 
   drainVmem();
   __syncthreads();
   if (c.tid == 0) {
-    if (a.smask) {
-      if (!coherent) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // every wave drained its stores before the barrier: the chunk is
+    // visible at the traffic's scope before the tail that announces it
 #pragma unroll
-      for (int j = 0; j < 3; ++j)
-        if (a.smask & (1 << j)) stAgent(s[j].tail, s[j].step + 1);
-    }
+    for (int j = 0; j < 3; ++j)
+      if (a.smask & (1 << j)) stCtr<SC>(s[j].tail, s[j].step + 1);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      if (a.rmask & (1 << i)) stAgent(r[i].head, r[i].step + 1);
+      if (a.rmask & (1 << i)) stCtr<SC>(r[i].head, r[i].step + 1);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -403,18 +437,20 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 
 // Credit wait shared by LL and LL128: the slot about to be written must have
 // been consumed NSLOTS steps ago.
+template <int SC>
 __device__ __forceinline__ bool waitCredits(const Ctx& c, Conn* s, int smask) {
   if (c.tid == 0) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      if (ok && (smask & (1 << j))) ok = waitCounter(c, s[j].head, creditTarget(s[j].step));
+      if (ok && (smask & (1 << j))) ok = waitCounter<SC>(c, s[j].head, creditTarget(s[j].step));
     if (!ok) *c.sAbort = 1;
   }
   __syncthreads();
   return !*(volatile int*)c.sAbort;
 }
 
+template <int SC>
 __device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, int rmask, int smask) {
   drainVmem();
   __syncthreads();
@@ -422,10 +458,10 @@ __device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, i
   if (c.tid == 0 && ok) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      if (rmask & (1 << i)) stAgent(r[i].head, r[i].step + 1);
+      if (rmask & (1 << i)) stCtr<SC>(r[i].head, r[i].step + 1);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      if (smask & (1 << j)) stAgent(s[j].tail, s[j].step + 1);
+      if (smask & (1 << j)) stCtr<SC>(s[j].tail, s[j].step + 1);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -439,18 +475,17 @@ __device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, i
 // ------------------------------------------------------------------ LL datapath
 // A lane handles a pair of 8-byte units (8 payload bytes, 16 FIFO bytes).
 
-template <int DT, int OP>
+template <int SC, int DT, int OP>
 __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   constexpr int E = ElemSize<DT>::value;
-  if (!waitCredits(c, s, a.smask)) return false;
-  const uint64_t slotB = c.comm->slotBytes[PROTO_LL];
+  if (!waitCredits<SC>(c, s, a.smask)) return false;
+  const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL];
   const uint64_t npairs = (a.nbytes + 7) / 8;
-  uint64_t* rin[3];
-  uint64_t* sout[3];
+  __amdgpu_buffer_rsrc_t rin[3], sout[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    rin[i] = (uint64_t*)(r[i].fifo + (r[i].step % NSLOTS) * slotB);
-    sout[i] = (uint64_t*)(s[i].fifo + (s[i].step % NSLOTS) * slotB);
+    rin[i] = makeRsrc(r[i].fifo + (r[i].step % NSLOTS) * (uint64_t)slotB, slotB);
+    sout[i] = makeRsrc(s[i].fifo + (s[i].step % NSLOTS) * (uint64_t)slotB, slotB);
   }
   const bool fast = (((uintptr_t)a.src | (uintptr_t)a.dst) & 7) == 0;
   const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
@@ -474,12 +509,13 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     for (int i = 0; i < 3; ++i) {
       if (alive && (a.rmask & (1 << i))) {
         const uint32_t flag = (uint32_t)(r[i].step + 1);
-        uint64_t u0 = ldAgent(rin[i] + 2 * p), u1 = ldAgent(rin[i] + 2 * p + 1);
+        const uint32_t uoff = (uint32_t)p * 16;
+        uint64_t u0 = ldUnit<SC>(rin[i], uoff), u1 = ldUnit<SC>(rin[i], uoff + 8);
         Spinner sp;
         while ((uint32_t)(u0 >> 32) != flag || (uint32_t)(u1 >> 32) != flag) {
           if (!sp.tick(c)) { alive = false; break; }
-          u0 = ldAgent(rin[i] + 2 * p);
-          u1 = ldAgent(rin[i] + 2 * p + 1);
+          u0 = ldUnit<SC>(rin[i], uoff);
+          u1 = ldUnit<SC>(rin[i], uoff + 8);
         }
         if (have) {
           acc[0] = redWord<DT, OP>(acc[0], (uint32_t)u0);
@@ -500,12 +536,12 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     for (int j = 0; j < 3; ++j) {
       if (a.smask & (1 << j)) {
         const uint64_t flag = (uint64_t)(uint32_t)(s[j].step + 1) << 32;
-        stAgent(sout[j] + 2 * p, (uint64_t)acc[0] | flag);
-        stAgent(sout[j] + 2 * p + 1, (uint64_t)acc[1] | flag);
+        stUnit<SC>(sout[j], (uint32_t)p * 16, (uint64_t)acc[0] | flag);
+        stUnit<SC>(sout[j], (uint32_t)p * 16 + 8, (uint64_t)acc[1] | flag);
       }
     }
   }
-  return finishFlagStep(c, r, s, a.rmask, a.smask);
+  return finishFlagStep<SC>(c, r, s, a.rmask, a.smask);
 }
 
 // ------------------------------------------------------------------ LL128 datapath
@@ -513,10 +549,10 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 // wave's group of 8 lines; lane 7 of each line carries 8 payload bytes and
 // the 8-byte flag.
 
-template <int DT, int OP>
+template <int SC, int DT, int OP>
 __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   constexpr int E = ElemSize<DT>::value;
-  if (!waitCredits(c, s, a.smask)) return false;
+  if (!waitCredits<SC>(c, s, a.smask)) return false;
   const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL128];
   const uint32_t nlines = (uint32_t)((a.nbytes + LL128_DATA - 1) / LL128_DATA);
   __amdgpu_buffer_rsrc_t rin[3], sout[3];
@@ -558,7 +594,7 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     for (int i = 0; i < 3; ++i) {
       if (alive && (a.rmask & (1 << i))) {
         const uint64_t flag = r[i].step + 1;
-        u32x4 v = act ? ldLine16(rin[i], loff) : u32x4{0, 0, 0, 0};
+        u32x4 v = act ? ldLine16<SC>(rin[i], loff) : u32x4{0, 0, 0, 0};
         Spinner sp;
         for (;;) {
           // lane 7 of each line holds the flag; the whole line is re-read
@@ -567,7 +603,7 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
           const bool lineOk = __shfl(flagOk, c.lid | 7) != 0;
           if (__all(lineOk)) break;
           if (__any(!sp.tick(c))) { alive = false; break; }
-          if (!lineOk) v = ldLine16(rin[i], loff);
+          if (!lineOk) v = ldLine16<SC>(rin[i], loff);
         }
         const uint32_t pw0 = v.x, pw1 = v.y, pw2 = (j < 7) ? v.z : 0u, pw3 = (j < 7) ? v.w : 0u;
         if (have) {
@@ -603,20 +639,20 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
             w.z = (uint32_t)flag;
             w.w = (uint32_t)(flag >> 32);
           }
-          stLine16(sout[q], loff, w);
+          stLine16<SC>(sout[q], loff, w);
         }
       }
     }
   }
   if (!alive) atomicOr(c.sAbort, 1);
-  return finishFlagStep(c, r, s, a.rmask, a.smask);
+  return finishFlagStep<SC>(c, r, s, a.rmask, a.smask);
 }
 
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ __forceinline__ bool step(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
-  if constexpr (PROTO == PROTO_SIMPLE) return stepSimple<DT, OP>(c, r, s, a);
-  else if constexpr (PROTO == PROTO_LL) return stepLL<DT, OP>(c, r, s, a);
-  else return stepLL128<DT, OP>(c, r, s, a);
+  if constexpr (PROTO == PROTO_SIMPLE) return stepSimple<SC, DT, OP>(c, r, s, a);
+  else if constexpr (PROTO == PROTO_LL) return stepLL<SC, DT, OP>(c, r, s, a);
+  else return stepLL128<SC, DT, OP>(c, r, s, a);
 }
 
 // ------------------------------------------------------------------ connections
@@ -633,6 +669,7 @@ __device__ __forceinline__ char* fifoOf(const Ctx& c, int proto, int receiver, i
 
 // Thread 0 reads the step counters (a receiver's own head, a sender's own
 // tail) and all threads pick them up from LDS.
+template <int SC>
 __device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, Conn* s, const int* speer,
                            const int* skind, uint64_t* sSteps) {
   const uint64_t fifoBytes = (uint64_t)NSLOTS * c.comm->slotBytes[proto];
@@ -654,8 +691,8 @@ __device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, C
   if (c.tid == 0) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      sSteps[i] = rkind[i] >= 0 ? ldAgent(r[i].head) : 0;
-      sSteps[3 + i] = speer[i] >= 0 ? ldAgent(s[i].tail) : 0;
+      sSteps[i] = rkind[i] >= 0 ? ldCtr<SC>(r[i].head) : 0;
+      sSteps[3 + i] = speer[i] >= 0 ? ldCtr<SC>(s[i].tail) : 0;
     }
   }
   __syncthreads();
@@ -676,12 +713,12 @@ __device__ __forceinline__ uint64_t roundUp(uint64_t a, uint64_t b) { return cei
 // Ring AllReduce, Section V-E table: step 0 send, 1..k-2 recvReduceSend,
 // k-1 recvReduceCopySend, k..2k-3 recvCopySend, 2k-2 recv.  At step t rank p
 // works on segment (p - 1 - t) mod k of the loop.
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
   Conn r[3], s[3];
   const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
-  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, A = 16 / E, K = w.chunk;
   const uint64_t loopCount = (uint64_t)R * K;
   const uint64_t full = w.chCount / loopCount, rem = w.chCount - full * loopCount;
@@ -726,19 +763,19 @@ __device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
         a.rmask = 1;
         a.recvDirect = direct;
       }
-      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+      if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
     }
   }
 }
 
 // Ring ReduceScatter, Section V-E table: step 0 send, 1..k-2 recvReduceSend,
 // k-1 recvReduceCopy; at step t rank p works on block (p - 1 - t) mod k.
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
   Conn r[3], s[3];
   const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
-  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, n = w.count, K = w.chunk;
   const char* sendb = args.send[me];
   char* recvb = args.recv[me];
@@ -752,7 +789,7 @@ __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArg
       a.rmask = t > 0 ? 1 : 0;
       a.smask = t < R - 1 ? 1 : 0;
       if (t == R - 1) a.dst = recvb + (w.chOffset + a0) * E;
-      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+      if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
     }
   }
 }
@@ -760,12 +797,12 @@ __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArg
 // Ring AllGather, Section V-E table: step 0 copySend (send in place),
 // 1..k-2 recvCopySend, k-1 recv; at step t rank p handles block (p - t) mod k.
 // Units are bytes.
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
   Conn r[3], s[3];
   const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
-  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t n = w.count, K = w.chunk;
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
   const char* sendb = args.send[me];
@@ -794,20 +831,20 @@ __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& a
         a.rmask = 1;
         a.recvDirect = direct;
       }
-      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+      if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
     }
   }
 }
 
 // Ring Broadcast, Section V-E table: a chain root -> root+1 -> ... -> root-1;
 // root copySend (send in place), middle recvCopySend, last recv.  Bytes.
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
   const int pos = ((me - w.root) % R + R) % R;
   Conn r[3], s[3];
   const int rk[3] = {pos > 0 ? 0 : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1}, sk[3] = {0, -1, -1};
-  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t K = w.chunk;
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
@@ -825,19 +862,19 @@ __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& a
       if (pos < R - 1) a.smask = 1;
     }
     if (direct && a.smask) a.sendDirect[0] = args.recv[nxt] + off;
-    if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
   }
 }
 
 // Ring Reduce, Section V-E table: a chain root+1 -> ... -> root; initiator
 // send, middle recvReduceSend, root recvReduceCopy.
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
   const int pos = ((me - w.root - 1) % R + 2 * R) % R;
   Conn r[3], s[3];
   const int rk[3] = {pos > 0 ? 0 : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1}, sk[3] = {0, -1, -1};
-  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, K = w.chunk;
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
     const uint64_t len = umin(K, w.chCount - a0);
@@ -848,7 +885,7 @@ __device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args
     a.rmask = pos > 0 ? 1 : 0;
     a.smask = pos < R - 1 ? 1 : 0;
     if (pos == R - 1) a.dst = args.recv[me] + off;
-    if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+    if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
   }
 }
 
@@ -857,7 +894,7 @@ __device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args
 // node is op(op(local, first child), second child).  Chunk iterations are
 // software-pipelined: the upward step of chunk j precedes the downward step
 // of chunk j - (NSLOTS - 1), which cannot deadlock with NSLOTS slots.
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int me = c.rank, t = w.tree;
   const int par = c.comm->parent[t][me];
@@ -869,7 +906,7 @@ __device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
   const int sp[3] = {par, nk > 0 ? k0 : -1, nk > 1 ? k1 : -1};
   const int sk[3] = {par >= 0 ? 1 + 3 * t + c.comm->childIdx[t][me] : -1, 3 + 3 * t, 3 + 3 * t};
   Conn r[3], s[3];
-  setupConns(c, PROTO, r, rk, s, sp, sk, sSteps);
+  setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const int upR = (nk > 0 ? 1 : 0) | (nk > 1 ? 2 : 0);
   const int downS = (nk > 0 ? 2 : 0) | (nk > 1 ? 4 : 0);
   const uint64_t E = w.elemBytes, K = w.chunk;
@@ -891,7 +928,7 @@ __device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
       } else {                   // middle: recvReduceSend; leaf: send
         a.smask = 1;
       }
-      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+      if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
     }
     if (j >= lag && par >= 0) {
       const uint64_t jd = j - lag, a0 = jd * K, len = umin(K, w.chCount - a0);
@@ -901,41 +938,93 @@ __device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
       a.dst = recvb + off;
       a.rmask = 4;
       a.smask = downS;           // middle: recvCopySend; leaf: recv
-      if (!step<PROTO, DT, OP>(c, r, s, a)) return;
+      if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
     }
   }
 }
 
-template <int PROTO, int DT, int OP>
+template <int PROTO, int SC, int DT, int OP>
 __device__ __noinline__ void runItem(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   if constexpr (OP == OP_COPY) {
-    if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, DT, OP>(c, w, args, sSteps);
-    else if (w.coll == COLL_BROADCAST) ringBroadcast<PROTO, DT, OP>(c, w, args, sSteps);
+    if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, SC, DT, OP>(c, w, args, sSteps);
+    else if (w.coll == COLL_BROADCAST) ringBroadcast<PROTO, SC, DT, OP>(c, w, args, sSteps);
   } else {
     if (w.coll == COLL_ALLREDUCE) {
-      if (w.algo == ALGO_TREE) treeAllReduce<PROTO, DT, OP>(c, w, args, sSteps);
-      else ringAllReduce<PROTO, DT, OP>(c, w, args, sSteps);
+      if (w.algo == ALGO_TREE) treeAllReduce<PROTO, SC, DT, OP>(c, w, args, sSteps);
+      else ringAllReduce<PROTO, SC, DT, OP>(c, w, args, sSteps);
     } else if (w.coll == COLL_REDUCESCATTER) {
-      ringReduceScatter<PROTO, DT, OP>(c, w, args, sSteps);
+      ringReduceScatter<PROTO, SC, DT, OP>(c, w, args, sSteps);
     } else if (w.coll == COLL_REDUCE) {
-      ringReduce<PROTO, DT, OP>(c, w, args, sSteps);
+      ringReduce<PROTO, SC, DT, OP>(c, w, args, sSteps);
     }
   }
 }
 
-template <int PROTO>
+template <int PROTO, int SC>
 __device__ void dispatchType(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int key = w.dtype * 4 + w.op;
   switch (key) {
-    case DT_I32 * 4 + OP_SUM: runItem<PROTO, DT_I32, OP_SUM>(c, w, args, sSteps); break;
-    case DT_I32 * 4 + OP_MAX: runItem<PROTO, DT_I32, OP_MAX>(c, w, args, sSteps); break;
-    case DT_F32 * 4 + OP_SUM: runItem<PROTO, DT_F32, OP_SUM>(c, w, args, sSteps); break;
-    case DT_F32 * 4 + OP_MAX: runItem<PROTO, DT_F32, OP_MAX>(c, w, args, sSteps); break;
-    case DT_BF16 * 4 + OP_SUM: runItem<PROTO, DT_BF16, OP_SUM>(c, w, args, sSteps); break;
-    case DT_BF16 * 4 + OP_MAX: runItem<PROTO, DT_BF16, OP_MAX>(c, w, args, sSteps); break;
-    case DT_U8 * 4 + OP_COPY: runItem<PROTO, DT_U8, OP_COPY>(c, w, args, sSteps); break;
+    case DT_I32 * 4 + OP_SUM: runItem<PROTO, SC, DT_I32, OP_SUM>(c, w, args, sSteps); break;
+    case DT_I32 * 4 + OP_MAX: runItem<PROTO, SC, DT_I32, OP_MAX>(c, w, args, sSteps); break;
+    case DT_F32 * 4 + OP_SUM: runItem<PROTO, SC, DT_F32, OP_SUM>(c, w, args, sSteps); break;
+    case DT_F32 * 4 + OP_MAX: runItem<PROTO, SC, DT_F32, OP_MAX>(c, w, args, sSteps); break;
+    case DT_BF16 * 4 + OP_SUM: runItem<PROTO, SC, DT_BF16, OP_SUM>(c, w, args, sSteps); break;
+    case DT_BF16 * 4 + OP_MAX: runItem<PROTO, SC, DT_BF16, OP_MAX>(c, w, args, sSteps); break;
+    case DT_U8 * 4 + OP_COPY: runItem<PROTO, SC, DT_U8, OP_COPY>(c, w, args, sSteps); break;
     default: break;
   }
+}
+
+__device__ __forceinline__ void dispatchItem(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  if (c.comm->scope == SCOPE_XCD && w.proto == PROTO_SIMPLE) {
+    dispatchType<PROTO_SIMPLE, SCOPE_XCD>(c, w, args, sSteps);
+  } else {
+    switch (w.proto) {
+      case PROTO_SIMPLE: dispatchType<PROTO_SIMPLE, SCOPE_DEVICE>(c, w, args, sSteps); break;
+      case PROTO_LL: dispatchType<PROTO_LL, SCOPE_DEVICE>(c, w, args, sSteps); break;
+      default: dispatchType<PROTO_LL128, SCOPE_DEVICE>(c, w, args, sSteps); break;
+    }
+  }
+}
+
+// Lane map.  With the XCD map, lane l lives on XCD (l % 8): every workgroup
+// reads the XCD it actually runs on and claims the next free (lane, rank)
+// role of that XCD from a per-XCD counter, so a lane's workgroups share one L2
+// by construction, whatever XCD the dispatcher starts from.  The counters
+// only grow; `claimBase` (the claims of all earlier launches, equal for every
+// XCD since launches are multiples of 8 workgroups dispatched round-robin) is
+// subtracted.  A claim beyond the launch's `perXcd` roles means the
+// workgroups were not spread evenly: that workgroup records an error and
+// raises the abort word so no lane waits on a role nobody holds.
+// Without the map, workgroup w is lane w / R, rank w % R.
+__device__ __forceinline__ bool claimRole(const DevComm* comm, uint32_t xcdMap, uint64_t claimBase, uint32_t perXcd,
+                                          uint32_t R, uint32_t* lane, uint32_t* rank, uint32_t* sRole) {
+  if (!xcdMap) {
+    *lane = blockIdx.x / R;
+    *rank = blockIdx.x % R;
+    return true;
+  }
+  if (threadIdx.x == 0) {
+    uint32_t x;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+    x &= 7u;
+    const uint64_t old = atomicAdd((unsigned long long*)(comm->claim + (uint64_t)x * CLAIM_STRIDE_U64), 1ull);
+    const uint64_t slot = old - claimBase;
+    uint32_t role = 0xFFFFFFFFu;
+    if (slot < perXcd) {
+      role = ((x + 8u * (uint32_t)(slot / R)) << 8) | (uint32_t)(slot % R);
+    } else {
+      orSystem32(comm->errorWord, ERR_PLACEMENT);
+      __hip_atomic_store(comm->abortFlag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    *sRole = role;
+  }
+  __syncthreads();
+  const uint32_t role = *sRole;
+  if (role == 0xFFFFFFFFu) return false;
+  *lane = role >> 8;
+  *rank = role & 0xFFu;
+  return true;
 }
 
 // ------------------------------------------------------------------ kernel
@@ -945,21 +1034,13 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
   __shared__ CollArgs sArgs;
   __shared__ uint64_t sSteps[6];
   __shared__ int sAbort;
+  __shared__ uint32_t sRole;
 
   const uint32_t R = d.nranks;
-  uint32_t lane, rank;
-  if (d.xcdMap) {
-    // workgroups are dispatched round-robin over the 8 XCDs; keep a lane's
-    // ranks on XCD (lane % 8) so its FIFO traffic stays in one L2
-    const uint32_t x = blockIdx.x & 7u, jj = blockIdx.x >> 3;
-    rank = jj % R;
-    lane = x + 8u * (jj / R);
-  } else {
-    lane = blockIdx.x / R;
-    rank = blockIdx.x % R;
-  }
-  if (lane >= d.nlanes) return;
   const DevComm* comm = d.comm;
+  uint32_t lane, rank;
+  if (!claimRole(comm, d.xcdMap, d.claimBase, d.perXcd, R, &lane, &rank, &sRole)) return;
+  if (lane >= d.nlanes) return;
   if ((comm->deadMask >> rank) & 1u) return;
 
   Ctx c;
@@ -986,15 +1067,101 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
     const CollArgs* as = inl ? &d.inlineArgs : &d.args[sItem.argsIndex];
     if (threadIdx.x < sizeof(CollArgs) / 8) ((uint64_t*)&sArgs)[threadIdx.x] = ((const uint64_t*)as)[threadIdx.x];
     __syncthreads();
-    switch (sItem.proto) {
-      case PROTO_SIMPLE: dispatchType<PROTO_SIMPLE>(c, sItem, sArgs, sSteps); break;
-      case PROTO_LL: dispatchType<PROTO_LL>(c, sItem, sArgs, sSteps); break;
-      default: dispatchType<PROTO_LL128>(c, sItem, sArgs, sSteps); break;
-    }
+    dispatchItem(c, sItem, sArgs, sSteps);
     __syncthreads();
     if (*(volatile int*)&sAbort) break;
     if (threadIdx.x == 0 && d.stamps && sItem.doneIndex != 0xFFFFFFFFu)
       d.stamps[(uint64_t)sItem.doneIndex * R + rank] = nowTicks();
+  }
+}
+
+// ------------------------------------------------------------------ serving kernel
+// Persistent: every (lane, rank) workgroup waits for its lane's next posted
+// entry, runs it like any work item, and publishes completion.  Exits on the
+// stop word (raised by the host, or by the first workgroup that waited
+// `idleTicks` without work), the abort word, or a failed wait.
+
+__device__ __forceinline__ uint64_t ldSystem64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
+  __shared__ WorkItem sItem;
+  __shared__ CollArgs sArgs;
+  __shared__ uint64_t sSteps[6];
+  __shared__ int sAbort;
+  __shared__ int sCmd;
+  __shared__ uint32_t sRole;
+
+  const uint32_t R = d.nranks;
+  uint32_t lane, rank;
+  if (!claimRole(d.comm, d.xcdMap, d.claimBase, d.perXcd, R, &lane, &rank, &sRole)) return;
+  if (lane >= d.nlanes) return;
+  Ctx c;
+  c.comm = d.comm;
+  c.rank = (int)rank;
+  c.lane = (int)lane;
+  c.nranks = (int)R;
+  c.tid = threadIdx.x;
+  c.nthreads = blockDim.x;
+  c.wave = threadIdx.x >> 6;
+  c.nwaves = (blockDim.x + 63) >> 6;
+  c.lid = threadIdx.x & 63;
+  c.sAbort = &sAbort;
+  if (threadIdx.x == 0) sAbort = 0;
+  uint64_t seq = d.startSeq[lane];
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int cmd = 0;
+      const uint64_t t0 = nowTicks();
+      uint64_t* dbg = d.dbg + ((uint64_t)lane * R + rank) * SERVE_STRIDE_U64;
+      for (uint32_t it = 0;; ++it) {
+        const uint64_t p = ldSystem64(d.posted + (uint64_t)lane * SERVE_STRIDE_U64);
+        if ((it & 1023u) == 0) {
+          __hip_atomic_store(dbg, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          __hip_atomic_store(dbg + 2, (uint64_t)it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        if (p > seq) {
+          cmd = 1;
+          __hip_atomic_store(dbg + 1, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          break;
+        }
+        if (ldSystem32(d.stop)) break;
+        __builtin_amdgcn_s_sleep(2);
+        if ((it & 63u) == 63u) {
+          if (ldSystem32(d.comm->abortFlag)) break;
+          if (nowTicks() - t0 > d.idleTicks) {
+            // the whole kernel stops together (a lane whose workgroups left
+            // could not run the work the host posts next); the host relaunches
+            // it when work arrives
+            __hip_atomic_store(d.stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            break;
+          }
+        }
+      }
+      sCmd = cmd;
+    }
+    __syncthreads();
+    if (sCmd != 1) break;
+    const ServeEntry* e = d.queue + (uint64_t)lane * SERVE_QUEUE + seq % SERVE_QUEUE;
+    if (threadIdx.x < sizeof(WorkItem) / 4)
+      ((uint32_t*)&sItem)[threadIdx.x] = __hip_atomic_load(((const uint32_t*)&e->item) + threadIdx.x,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x < sizeof(CollArgs) / 8)
+      ((uint64_t*)&sArgs)[threadIdx.x] = ldSystem64(((const uint64_t*)&e->args) + threadIdx.x);
+    __syncthreads();
+    dispatchItem(c, sItem, sArgs, sSteps);
+    drainVmem();
+    __syncthreads();
+    if (*(volatile int*)&sAbort) break;
+    if (threadIdx.x == 0) {
+      // outputs visible to the host and to later kernels before completion
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      __hip_atomic_store(d.done + ((uint64_t)lane * R + rank) * SERVE_STRIDE_U64, seq + 1, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    ++seq;
   }
 }
 
@@ -1056,7 +1223,7 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
             v.z = (uint32_t)flag;
             v.w = (uint32_t)(flag >> 32);
           }
-          stLine16(rs, line * LL128_LINE + 16 * j, v);
+          stLine16<SCOPE_DEVICE>(rs, line * LL128_LINE + 16 * j, v);
         }
       }
     } else {
@@ -1064,7 +1231,7 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
         const int line = L0 + g;
         const bool act = line < lines;
         const uint32_t loff = (uint32_t)line * LL128_LINE + 16u * j;
-        u32x4 v = act ? ldLine16(rs, loff) : u32x4{0, 0, 0, 0};
+        u32x4 v = act ? ldLine16<SCOPE_DEVICE>(rs, loff) : u32x4{0, 0, 0, 0};
         const uint64_t t0 = nowTicks();
         bool tornSeen = false;
         for (;;) {
@@ -1083,7 +1250,7 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
           const bool done = lineOk && lineData;
           if (__all(done)) break;
           if (__any(nowTicks() - t0 > maxTicks)) { atomicOr(&sFail, 1); break; }
-          if (!done && act) v = ldLine16(rs, loff);
+          if (!done && act) v = ldLine16<SCOPE_DEVICE>(rs, loff);
         }
         if (act && j == 0) checked++;
         if (*(volatile int*)&sFail) break;
@@ -1113,6 +1280,15 @@ hipError_t vcclLaunchColl(const vccl::LaunchDesc& d, int grid, int block, hipStr
 
 hipError_t vcclCollOccupancy(int block, int* blocksPerCU) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocksPerCU, (const void*)vccl::collKernel, block, 0);
+}
+
+hipError_t vcclLaunchServe(const vccl::ServeDesc& d, int grid, int block, hipStream_t stream) {
+  void* args[] = {(void*)&d};
+  return hipLaunchKernel((const void*)vccl::serveKernel, dim3(grid), dim3(block), args, 0, stream);
+}
+
+hipError_t vcclServeOccupancy(int block, int* blocksPerCU) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocksPerCU, (const void*)vccl::serveKernel, block, 0);
 }
 
 hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream) {

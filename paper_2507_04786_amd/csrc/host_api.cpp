@@ -27,9 +27,10 @@ thread_local GroupState tlsGroup;
 bool validHandle(vcclComm_t comm) { return comm && comm->clique && !comm->destroyed; }
 
 vcclResult_t asyncStatus(Clique* c) {
-  if (c->aborted) return vcclRemoteError;
   const uint32_t e = __atomic_load_n(c->hError, __ATOMIC_ACQUIRE);
-  return e ? vcclRemoteError : vcclSuccess;
+  if (e & ERR_PLACEMENT) return vcclInternalError;
+  if (c->aborted || e) return vcclRemoteError;
+  return vcclSuccess;
 }
 
 // Joins the streams of every rank involved: the launch stream waits for all
@@ -59,6 +60,7 @@ vcclResult_t launchPrepared(Clique* c, LaunchDesc& d, int grid, int block, const
     logError("kernel launch", e, __FILE__, __LINE__);
     return vcclUnhandledHipError;
   }
+  if (c->xcdMap) c->claimBase += d.perXcd;
   VCCL_HIPCHECK(hipEventRecord(c->lastLaunchDone, ls));
   for (int i = 0; i < ss.n - 1; ++i) VCCL_HIPCHECK(hipStreamWaitEvent(ss.list[i], c->lastLaunchDone, 0));
   return vcclSuccess;
@@ -69,6 +71,7 @@ vcclResult_t launchPrepared(Clique* c, LaunchDesc& d, int grid, int block, const
 vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool grouped) {
   vcclResult_t st = asyncStatus(c);
   if (st != vcclSuccess) return st;
+  if (c->serving) return vcclInvalidUsage;  // the serving kernel owns the lanes
   std::vector<Coll> colls;
   for (const auto& x : collsIn)
     if (x.count > 0) colls.push_back(x);
@@ -167,6 +170,8 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   }
   d.nlanes = (uint32_t)nlanes;
   const int grid = c->xcdMap ? 8 * R * ((nlanes + 7) / 8) : R * nlanes;
+  d.perXcd = (uint32_t)(R * ((nlanes + 7) / 8));
+  d.claimBase = c->claimBase;
   const int occ = cliqueOccupancy(c, block);
   if (grid > c->numCUs * occ) return vcclInternalError;
   r = launchPrepared(c, d, grid, block, ss);
@@ -183,6 +188,7 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   info.nitems = (int)nitems;
   info.ncolls = (int)colls.size();
   info.grid = grid;
+  info.scope = (int)c->host.scope;
   (void)grouped;
   return vcclSuccess;
 }
@@ -298,6 +304,9 @@ static vcclResult_t enqueueCall(vcclComm_t comm, const Call& call) {
   if (((uintptr_t)call.send % E) || ((uintptr_t)call.recv % E)) return vcclInvalidArgument;
   if (call.count > ((size_t)1 << 40)) return vcclInvalidArgument;
   c->pending[me].push_back(call);
+  if (tlsGroup.depth > 0 &&
+      std::find(tlsGroup.touched.begin(), tlsGroup.touched.end(), c) == tlsGroup.touched.end())
+    tlsGroup.touched.push_back(c);  // checked for unmatched calls at GroupEnd
   for (int r = 0; r < R; ++r)
     if (c->pending[r].empty()) return vcclSuccess;  // wait for the other ranks
   Coll coll{};
@@ -321,8 +330,6 @@ static vcclResult_t enqueueCall(vcclComm_t comm, const Call& call) {
   if (mismatch != vcclSuccess) return mismatch;
   if (tlsGroup.depth > 0) {
     tlsGroup.colls.push_back({c, coll});
-    if (std::find(tlsGroup.touched.begin(), tlsGroup.touched.end(), c) == tlsGroup.touched.end())
-      tlsGroup.touched.push_back(c);
     return vcclSuccess;
   }
   std::vector<Coll> one{coll};

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "host_internal.h"
 
@@ -108,10 +109,8 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   };
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return fail(e, "hipSetDevice");
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, device);
-  if (e != hipSuccess) return fail(e, "hipGetDeviceProperties");
-  c->numCUs = prop.multiProcessorCount;
+  e = hipDeviceGetAttribute(&c->numCUs, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return fail(e, "hipDeviceGetAttribute");
   int wallKHz = 0;
   if (hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, device) == hipSuccess && wallKHz > 0)
     c->ticksPerUs = wallKHz / 1000.0;
@@ -135,6 +134,11 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   if (e != hipSuccess) return fail(e, "hipMalloc(counters)");
   e = hipMemset(c->ctr, 0, nconn * CTR_RECORD_U64 * sizeof(uint64_t));
   if (e != hipSuccess) return fail(e, "hipMemset(counters)");
+  e = hipMalloc((void**)&c->claim, 8 * CLAIM_STRIDE_U64 * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(e, "hipMalloc(claim)");
+  e = hipMemset(c->claim, 0, 8 * CLAIM_STRIDE_U64 * sizeof(uint64_t));
+  if (e != hipSuccess) return fail(e, "hipMemset(claim)");
+  c->host.claim = c->claim;
   e = hipHostMalloc((void**)&c->hAbort, 256, hipHostMallocCoherent);
   if (e != hipSuccess) return fail(e, "hipHostMalloc(abort)");
   e = hipHostMalloc((void**)&c->hError, 256, hipHostMallocCoherent);
@@ -147,7 +151,7 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   const double timeoutUs = (double)envLong("VCCL_TIMEOUT_US", 5000000);
   c->host.timeoutTicks = (uint64_t)(timeoutUs * c->ticksPerUs);
   c->host.deadMask = 0;
-  c->host.simpleMode = envStr("VCCL_SIMPLE_SYNC") == "fence" ? SIMPLE_FENCE : SIMPLE_COHERENT;
+  c->host.scope = SCOPE_DEVICE;
   c->host.ctr = c->ctr;
   c->host.abortFlag = c->hAbort;
   c->host.errorWord = c->hError;
@@ -187,6 +191,15 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   // device holds at once (grid <= CUs * occupancy), and every wait is bounded
   c->cooperative = envStr("VCCL_LAUNCH") == "cooperative";
   c->xcdMap = (int)envLong("VCCL_XCD_MAP", 1);
+  // XCD-local chunk traffic (opt-in: measured no faster than device scope on
+  // the ring AllReduce) needs the lane map, which claims every lane's roles
+  // on one XCD at kernel start
+  if (c->xcdMap && envStr("VCCL_SCOPE") == "xcd") {
+    c->host.scope = SCOPE_XCD;
+    e = hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(e, "hipMemcpy(devcomm)");
+  }
+  logInfo("traffic scope %s", c->host.scope == SCOPE_XCD ? "xcd" : "device");
   *out = c;
   return vcclSuccess;
 }
@@ -200,6 +213,7 @@ void cliqueFree(Clique* c) {
     if (c->treeFifo[p]) hipFree(c->treeFifo[p]);
   }
   if (c->ctr) hipFree(c->ctr);
+  if (c->claim) hipFree(c->claim);
   if (c->dcomm) hipFree(c->dcomm);
   if (c->dItems) hipFree(c->dItems);
   if (c->dLaneStart) hipFree(c->dLaneStart);

@@ -16,6 +16,8 @@
 hipError_t vcclLaunchColl(const vccl::LaunchDesc& d, int grid, int block, hipStream_t stream, bool cooperative);
 hipError_t vcclCollOccupancy(int block, int* blocksPerCU);
 hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream);
+hipError_t vcclLaunchServe(const vccl::ServeDesc& d, int grid, int block, hipStream_t stream);
+hipError_t vcclServeOccupancy(int block, int* blocksPerCU);
 hipError_t vcclLaunchTearProbe(char* bufs, uint64_t* acks, int pairs, int lines, int rounds,
                                unsigned long long* counts, uint64_t maxTicks, uint32_t* failed, hipStream_t stream);
 
@@ -90,6 +92,9 @@ struct Clique {
   bool aborted = false;
   std::vector<vcclComm*> handles;
   int occupancy[17] = {0};    // blocks per CU for nthreads = 64 * index
+  bool serving = false;       // a persistent serving kernel owns the lanes
+  uint64_t* claim = nullptr;  // per-XCD role counters (device)
+  uint64_t claimBase = 0;     // role claims of all launches so far, per XCD
 };
 
 Clique* cliqueOf(vcclComm_t comm);

@@ -74,7 +74,8 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));
   // --- workgroup size
-  long dfltT = (proto == PROTO_SIMPLE || S >= (256u << 10)) ? 512 : 256;
+  long dfltT = (S >= (256u << 10)) ? 512 : 256;
+  if (proto == PROTO_SIMPLE) dfltT = 256;
   int nthreads = (int)pickPos(c->apiTune.nthreads, c->envTune.nthreads, dfltT);
   nthreads = std::max(64, std::min(1024, nthreads / 64 * 64));
   // co-residency: every workgroup of the launch must be resident at once
@@ -97,7 +98,7 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
       // every channel at least one full loop
       const uint64_t chBytes = ceilDiv(S, (uint64_t)nch);
       chunk = roundUp(std::max<uint64_t>(ceilDiv(chBytes, (uint64_t)R), 16 * 1024), 4096);
-      chunk = std::min<uint64_t>(chunk, maxChunk);
+      chunk = std::min<uint64_t>(chunk, 128 * 1024);  // measured best for large rings
     } else {
       chunk = maxChunk;
     }

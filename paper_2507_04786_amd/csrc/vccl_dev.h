@@ -39,31 +39,29 @@ constexpr uint32_t SLOT_BYTES_LL128 = 600u * 1024u;
 constexpr uint32_t LL128_LINE = 128, LL128_DATA = 120;
 constexpr uint32_t CTR_RECORD_U64 = 32;  // 256 B per connection
 constexpr uint32_t CTR_HEAD_U64 = 16;    // head at +128 B
+constexpr uint32_t CLAIM_STRIDE_U64 = 16;
 
-// Simple-protocol synchronisation modes.
-//  SIMPLE_FENCE: plain stores, device-scope release fence (L2 write-back)
-//    before the tail store; device-scope acquire (L2 invalidate) after it.
-//  SIMPLE_COHERENT: the chunk itself is stored and loaded with device-scope
-//    coherent accesses (sc1, as relaxed device-scope atomics are), so a drain
-//    of the stores before the tail store orders them and no cache-wide
-//    write-back or invalidate is needed.
-constexpr uint32_t SIMPLE_FENCE = 0, SIMPLE_COHERENT = 1;
+// Scope of the Simple protocol's bulk data traffic between the workgroups of
+// a lane (see device.hip): SCOPE_DEVICE -- anywhere on the device;
+// SCOPE_XCD -- through one XCD's L2.  Flags and counters: device scope.
+constexpr uint32_t SCOPE_DEVICE = 0, SCOPE_XCD = 1;
 
 // device-side error codes (bit flags in the error word)
-constexpr uint32_t ERR_TIMEOUT = 1u, ERR_ABORT = 2u;
+constexpr uint32_t ERR_TIMEOUT = 1u, ERR_ABORT = 2u, ERR_PLACEMENT = 4u;
 
 struct DevComm {
   int32_t nranks;
   int32_t maxLanes;
   uint64_t timeoutTicks;        // device wall-clock ticks a single wait may take
   uint32_t deadMask;            // test hook: ranks whose workgroups do nothing
-  uint32_t simpleMode;          // Simple protocol synchronisation, SIMPLE_* below
+  uint32_t scope;               // SCOPE_DEVICE or SCOPE_XCD for every launch of the set
   char* fifo[3];                // ring connections, per protocol
   char* treeFifo[3];            // tree connections, per protocol (null until first used)
   uint64_t slotBytes[3];
   uint64_t* ctr;                // counters
   uint32_t* abortFlag;          // host-pinned, written by the host
   uint32_t* errorWord;          // host-pinned, written by the device
+  uint64_t* claim;              // per-XCD role counters (CLAIM_STRIDE_U64 apart)
   int8_t parent[2][MAX_RANKS];
   int8_t child[2][MAX_RANKS][2];
   int8_t childIdx[2][MAX_RANKS];  // my position among my parent's children
@@ -99,9 +97,36 @@ struct LaunchDesc {
   uint32_t nlanes;
   uint32_t nranks;
   uint32_t xcdMap;              // 1: lane l's workgroups share XCD (l % 8)
-  uint32_t pad;
+  uint32_t perXcd;              // roles per XCD in this launch (grid = 8 * perXcd)
+  uint64_t claimBase;           // role claims of all earlier launches, per XCD
   CollArgs inlineArgs;
   WorkItem inlineItems[MAX_INLINE];
+};
+
+// ---------------------------------------------------------------- serving
+// Per-lane request queues live in pinned host memory: the host writes an
+// entry, then bumps the lane's `posted` counter; every workgroup of the lane
+// runs the entry and then publishes its own `done` counter (with a
+// system-scope release, so the outputs are visible to later work).
+constexpr int SERVE_QUEUE = 4;
+constexpr int SERVE_STRIDE_U64 = 16;  // counters 128 B apart
+
+struct ServeEntry {
+  WorkItem item;
+  CollArgs args;
+};
+
+struct ServeDesc {
+  const DevComm* comm;
+  ServeEntry* queue;        // [nlanes][SERVE_QUEUE]
+  uint64_t* posted;         // [nlanes] * SERVE_STRIDE_U64
+  uint64_t* done;           // [nlanes * nranks] * SERVE_STRIDE_U64
+  uint32_t* stop;           // set by the host to end the kernel
+  uint64_t* dbg;            // per (lane, rank): last posted value seen, items picked up, polls
+  uint64_t idleTicks;       // the kernel exits after this long without work
+  uint32_t nlanes, nranks, xcdMap, perXcd;
+  uint64_t claimBase;
+  uint64_t startSeq[MAX_LANES];
 };
 
 }  // namespace vccl

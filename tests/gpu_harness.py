@@ -76,3 +76,20 @@ def tune(vccl, comms, algo="ring", proto="simple", nchannels=1, chunk=0, nthread
 
 def untune(vccl, comms):
     vccl.vcclCommSetTuning(comms[0])
+
+
+def init_comms(vccl, R, scope="auto"):
+    """Communicator set; scope "xcd" / "device" selects the Simple protocol's
+    chunk traffic scope (VCCL_SCOPE), "auto" the library default."""
+    import os
+    old = os.environ.get("VCCL_SCOPE")
+    if scope in ("device", "xcd"):
+        os.environ["VCCL_SCOPE"] = scope
+    try:
+        return vccl.vcclCommInitAll(R)
+    finally:
+        if scope in ("device", "xcd"):
+            if old is None:
+                del os.environ["VCCL_SCOPE"]
+            else:
+                os.environ["VCCL_SCOPE"] = old

@@ -27,10 +27,11 @@ _CLIQUES = {}
 
 @pytest.fixture(scope="module")
 def comms_for(vccl):
-    def get(R):
-        if R not in _CLIQUES:
-            _CLIQUES[R] = vccl.vcclCommInitAll(R)
-        return _CLIQUES[R]
+    def get(R, scope="auto"):
+        key = (R, scope)
+        if key not in _CLIQUES:
+            _CLIQUES[key] = H.init_comms(vccl, R, scope)
+        return _CLIQUES[key]
     yield get
     for cs in _CLIQUES.values():
         for c in cs:
@@ -269,3 +270,31 @@ def test_large_allreduce_sampled_and_bounded(vccl, comms_for):
         _assert_bits(out0[idx], want, f"large {proto} sampled")
         err = np.abs(out0.astype(np.float64) - defs.fp64_sum(xs, "float32"))
         assert (err <= defs.sum_error_bound(xs, "float32") * (1 + 1e-9)).all()
+
+
+@pytest.mark.parametrize("proto", PROTOS)
+def test_xcd_scope_path(vccl, comms_for, proto):
+    """Opt-in path: the Simple protocol's chunks travel through the L2 of the
+    XCD every workgroup of the lane was placed on (flags stay device scope)."""
+    for (R, n, C, chunk) in [(4, 70001, 4, 4096), (16, 3001, 3, 512), (8, 65543, 9, 2048)]:
+        comms = comms_for(R, "xcd")
+        for coll, algo in (("allreduce", "ring"), ("allreduce", "tree"), ("reducescatter", "ring"),
+                           ("allgather", "ring")):
+            xs = _inputs(R, "float32", H.send_len(coll, n, R), extra=5)
+            H.tune(vccl, comms, algo, proto, nchannels=C, chunk=chunk)
+            try:
+                got = _run(vccl, comms, coll, xs, n, "float32")
+                assert vccl.vcclCommGetLastPlan(comms[0])["scope"] == 1
+            finally:
+                H.untune(vccl, comms)
+            want = sim.run(coll, xs, dtype="float32", nchannels=C, chunk_bytes=chunk, algo=algo)
+            for r in range(R):
+                _assert_bits(got[r], want[r], f"xcd scope {coll} {algo} {proto} R={R} rank {r}")
+
+
+def test_device_scope_is_the_default(vccl, comms_for):
+    comms = comms_for(8)
+    xs = _inputs(8, "int32", 1000)
+    got = _run(vccl, comms, "allreduce", xs, 1000, "int32")
+    assert vccl.vcclCommGetLastPlan(comms[0])["scope"] == 0
+    _assert_bits(got[0], defs.allreduce(xs, "sum", "int32")[0], "device scope")

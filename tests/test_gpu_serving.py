@@ -1,0 +1,155 @@
+"""Serving: continuous batching over a persistent kernel.  Requests admitted
+while others run overlap on the device; each result is the same bits alone
+and in the mix, and matches the oracle."""
+import numpy as np
+import pytest
+
+import synthetic_inputs as si
+from oracle import definitions as defs
+from oracle import folds
+from tests import gpu_harness as H
+
+pytestmark = pytest.mark.gpu
+
+R = 8
+KINDS = [(0.6, "allreduce"), (0.2, "allgather"), (0.2, "reducescatter")]
+CODES = {"allreduce": 0, "broadcast": 1, "reduce": 2, "allgather": 3, "reducescatter": 4}
+
+
+@pytest.fixture(scope="module")
+def vccl():
+    import paper_2507_04786_amd as v
+    return v
+
+
+def _requests(seed, count, lo, hi):
+    rng = si.rng_for(si.WL_SERVING, 0, seed)
+    sizes = si.log_uniform_sizes(rng, count, lo, hi)
+    reqs = []
+    for i in range(count):
+        u = rng.uniform()
+        coll = "allreduce" if u < 0.6 else ("allgather" if u < 0.8 else "reducescatter")
+        dtype = ["float32", "bfloat16", "int32"][int(rng.integers(0, 3))]
+        E = H.ELEM[dtype]
+        n = max(1, int(sizes[i]) // E // (R if coll != "allreduce" else 1))
+        kw = dict(lo=-2**20, hi=2**20) if dtype == "int32" else {}
+        xs = si.rank_inputs(si.WL_SERVING, R, dtype, H.send_len(coll, n, R), extra=seed * 10000 + i, **kw)
+        reqs.append((coll, dtype, n, xs))
+    return reqs
+
+
+def _buffers(reqs):
+    bufs = []
+    for coll, dtype, n, xs in reqs:
+        sends = [H.to_dev(x) for x in xs]
+        recvs = [H.empty_dev(H.recv_len(coll, n, R), dtype) for _ in range(R)]
+        bufs.append((sends, recvs))
+    H.torch().cuda.synchronize()
+    return bufs
+
+
+def _submit(vccl, srv, req, buf):
+    coll, dtype, n, _ = req
+    return vccl.vcclServeSubmit(srv, CODES[coll], vccl.DTYPE_NAMES[dtype], vccl.vcclSum, 0, n, buf[0], buf[1])
+
+
+def _wait(vccl, srv, ids):
+    import time
+    pending = set(ids)
+    deadline = time.time() + 60
+    while pending and time.time() < deadline:
+        for rid in list(pending):
+            done, status, _ = vccl.vcclServeTest(srv, rid)
+            if done:
+                assert status == vccl.vcclSuccess
+                pending.discard(rid)
+    assert not pending, "requests did not complete"
+
+
+def _snapshot(bufs, reqs):
+    return [[H.from_dev(r, req[1]).copy() for r in buf[1]] for buf, req in zip(bufs, reqs)]
+
+
+def test_alone_equals_mix_and_oracle(vccl):
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        reqs = _requests(1, 40, 1024, 4 << 20)
+        bufs = _buffers(reqs)
+        srv = vccl.vcclServeCreate(comms, 4 << 30, 16)
+        try:
+            alone = []
+            # no device-wide synchronisation while the persistent kernel runs
+            # (it would wait for the kernel's idle exit): completion is
+            # published with a system-scope release, so plain copies suffice
+            for req, buf in zip(reqs, bufs):
+                _wait(vccl, srv, [_submit(vccl, srv, req, buf)])
+                alone.append([H.from_dev(r, req[1]).copy() for r in buf[1]])
+                for r in buf[1]:
+                    r.view(H.torch().uint8).fill_(0x5A)
+                H.torch().cuda.current_stream().synchronize()
+            ids = [_submit(vccl, srv, req, buf) for req, buf in zip(reqs, bufs)]
+            _wait(vccl, srv, ids)
+            mix = _snapshot(bufs, reqs)
+        finally:
+            vccl.vcclServeDestroy(srv)
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+        for k, (coll, dtype, n, xs) in enumerate(reqs):
+            for r in range(R):
+                assert np.array_equal(alone[k][r].view(np.uint8), mix[k][r].view(np.uint8)), (k, coll, dtype, n, r)
+            if coll == "allgather":
+                want = defs.allgather(xs)
+            elif dtype == "int32":
+                want = (defs.allreduce if coll == "allreduce" else defs.reducescatter)(xs, "sum", "int32")
+            elif coll == "reducescatter":
+                want = [folds.ring_reducescatter(xs, "sum", dtype, r) for r in range(R)]
+            else:
+                want = None
+            if want is not None:
+                for r in range(R):
+                    assert np.array_equal(mix[k][r].view(np.uint8), want[r].view(np.uint8)), (k, coll, dtype, r)
+            else:
+                # float AllReduce: every rank identical, within the fp64 bound
+                for r in range(1, R):
+                    assert np.array_equal(mix[k][r].view(np.uint8), mix[k][0].view(np.uint8))
+                err = np.abs(H_to64(dtype, mix[k][0]) - defs.fp64_sum(xs, dtype))
+                assert (err <= defs.sum_error_bound(xs, dtype) * (1 + 1e-9) + 1e-30).all()
+        # after the server the per-call path works again on the same lanes
+        x = [H.to_dev(np.full(8, r, np.int32)) for r in range(R)]
+        for r in range(R):
+            vccl.vcclAllReduce(x[r], x[r], 8, vccl.vcclInt32, vccl.vcclSum, comms[r])
+        H.torch().cuda.synchronize()
+        assert int(x[0][0].item()) == 28
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+
+
+def H_to64(dtype, a):
+    from oracle import elementwise as ew
+    return ew.to_float64(dtype, a)
+
+
+def test_poisson_replay_reports_latencies(vccl):
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        reqs = _requests(2, 200, 1024, 1 << 20)
+        bufs = _buffers(reqs)
+        srv = vccl.vcclServeCreate(comms, 4 << 30, 16)
+        try:
+            with pytest.raises(vccl.VcclError) as e:  # the lanes belong to the server
+                t = H.torch().zeros(4, device="cuda")
+                for r in range(R):
+                    vccl.vcclAllReduce(t, t, 4, vccl.vcclFloat32, vccl.vcclSum, comms[r])
+            assert e.value.code == vccl.vcclInvalidUsage
+            arr = si.poisson_arrivals(si.rng_for(si.WL_SERVING, 1), len(reqs), 20000.0)
+            objs = [vccl.make_request(CODES[c], vccl.DTYPE_NAMES[d], vccl.vcclSum, 0, n, b[0], b[1])
+                    for (c, d, n, _), b in zip(reqs, bufs)]
+            lat, st = vccl.vcclServeReplay(srv, objs, (arr * 1e9).astype(np.int64))
+        finally:
+            vccl.vcclServeDestroy(srv)
+        assert all(s == vccl.vcclSuccess for s in st)
+        assert all(x > 0 for x in lat)
+        assert np.percentile(lat, 99) < 1e9
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
