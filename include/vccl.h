@@ -47,7 +47,7 @@ extern "C" {
 #define VCCL_MAJOR 0
 #define VCCL_MINOR 1
 #define VCCL_MAX_RANKS 16
-#define VCCL_MAX_CHANNELS 32
+#define VCCL_MAX_CHANNELS 64
 
 typedef struct vcclComm* vcclComm_t;
 

@@ -34,7 +34,7 @@ vcclSum, vcclMax = 0, 1
 vcclAlgoAuto, vcclAlgoRing, vcclAlgoTree = -1, 0, 1
 vcclProtoAuto, vcclProtoSimple, vcclProtoLL, vcclProtoLL128 = -1, 0, 1, 2
 VCCL_MAX_RANKS = 16
-VCCL_MAX_CHANNELS = 32
+VCCL_MAX_CHANNELS = 64
 
 COLL_ALLREDUCE, COLL_BROADCAST, COLL_REDUCE, COLL_ALLGATHER, COLL_REDUCESCATTER = 0, 1, 2, 3, 4
 

@@ -6,10 +6,11 @@
 // HBM under one of three protocols (Section III):
 //
 //  * Simple: a slot holds a whole chunk.  The sender waits for a free slot
-//    (head counter), stores the chunk, makes it visible at device scope
-//    (every wave drains its stores, then one release fence) and publishes the
-//    tail counter; the receiver waits on tail, acquires, reads the slot and
-//    returns the slot through head.  The receiver waits for the full chunk.
+//    (head counter), stores the chunk with device-scope coherent stores,
+//    drains them (every wave waits for its stores, then a barrier) and
+//    publishes the tail counter; the receiver waits on tail, reads the slot
+//    with device-scope coherent loads and returns the slot through head.
+//    The receiver waits for the full chunk.
 //  * LL: every 8-byte unit carries 4 bytes of data and a 4-byte flag and is
 //    written and read by one 64-bit device-scope atomic access, so no fence
 //    is needed; the receiver polls each unit's flag.

@@ -69,7 +69,8 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   // --- channels: one workgroup per CU at most (R * C <= 256), and enough
   // bytes per channel to amortise the per-step synchronisation
   const uint64_t perCh = proto == PROTO_SIMPLE ? 512 * 1024 : 16 * 1024;
-  const int laneCap = std::max(1, std::min(c->maxLanes, c->numCUs / R));
+  // up to two workgroups per CU: while one waits on a flag the other moves data
+  const int laneCap = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
   long dfltC = (long)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)laneCap, S / perCh));
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));

@@ -31,7 +31,7 @@ enum : uint8_t { OP_SUM = 0, OP_MAX = 1, OP_COPY = 2 };
 constexpr int NSLOTS = 8;
 constexpr int NCONN = 7;
 constexpr int MAX_RANKS = 16;
-constexpr int MAX_LANES = 32;
+constexpr int MAX_LANES = 64;
 constexpr int MAX_INLINE = 32;
 constexpr uint32_t SLOT_BYTES_SIMPLE = 512u * 1024u;
 constexpr uint32_t SLOT_BYTES_LL = 32u * 1024u;
