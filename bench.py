@@ -10,10 +10,17 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
               duration (HIP events on the launch stream over the timed
               region) against the 8 TB/s HBM3E peak
   protocols   the same AllReduce forced to each protocol (busBW, HBM fraction)
+  grouped     64 mixed collectives (AR/AG/RS, 4 KiB..16 MiB log-uniform, fp32 /
+              bf16 / int32) in one GroupStart/GroupEnd launch against one
+              launch per collective, and the same for a batch of sub-1 MiB
+              collectives; bit equality of the two paths is checked
+  serving     Poisson request streams (AR 60 % / AG 20 % / RS 20 %, 1 KiB..128 MiB
+              log-uniform) replayed through the continuous-batching server at
+              several arrival rates: p50 / p99 latency, offered vs achieved rate
   cpu_baseline the CPU oracle (numpy schedule simulation) on the same inputs
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib 64]
-                       [--no-cpu] [--no-protocols]
+                       [--no-cpu] [--no-protocols] [--no-grouped] [--no-serving]
 """
 from __future__ import annotations
 
@@ -61,6 +68,162 @@ def load_traffic(kernel_key: str):
         return None
 
 
+COLL_CODES = {"allreduce": 0, "broadcast": 1, "reduce": 2, "allgather": 3, "reducescatter": 4}
+DTYPES = ("float32", "bfloat16", "int32")
+ELEM = {"float32": 4, "bfloat16": 2, "int32": 4}
+
+
+def _send_arenas(torch, si, workload, R, nbytes):
+    """Per (dtype, rank): nbytes of seeded synthetic values on the device
+    (fp32 N(0,1), bf16 U(-1,1), int32 U[-2^20, 2^20]), built by tiling a
+    4 MiB draw.  Collectives read slices of these; they are never written."""
+    import numpy as np
+    out = {}
+    tile = 4 << 20
+    for dt in DTYPES:
+        E = ELEM[dt]
+        kw = dict(lo=-2 ** 20, hi=2 ** 20) if dt == "int32" else {}
+        per = []
+        for r in range(R):
+            x = si.draw(dt, tile // E, si.rng_for(workload, r, 77), **kw)
+            t = torch.from_numpy(np.ascontiguousarray(x).view(np.uint8)).cuda()
+            per.append(t.repeat(max(1, nbytes // tile)))
+        out[dt] = per
+    return out
+
+
+def _batch_specs(si, seed, count, lo, hi, R):
+    rng = si.rng_for(si.WL_GROUPED, 0, seed)
+    sizes = si.log_uniform_sizes(rng, count, lo, hi)
+    specs = []
+    for i in range(count):
+        coll = ("allreduce", "allgather", "reducescatter")[int(rng.integers(0, 3))]
+        dt = DTYPES[int(rng.integers(0, 3))]
+        E = ELEM[dt]
+        n = max(1, int(sizes[i]) // E // (R if coll != "allreduce" else 1))
+        specs.append((coll, dt, n))
+    return specs
+
+
+def grouped_leg(vccl, torch, si, comms, stream, reps=10):
+    """64 collectives issued in one group against 64 separate launches
+    (device time between events on the launch stream, and host wall time)."""
+    import numpy as np
+    R = len(comms)
+    arenas = _send_arenas(torch, si, si.WL_GROUPED, R, 16 << 20)
+    codes = {"float32": vccl.vcclFloat32, "bfloat16": vccl.vcclBfloat16, "int32": vccl.vcclInt32}
+    result = {}
+    for name, lo, hi in (("mixed_4KiB_16MiB", 4 << 10, 16 << 20), ("sub_1MiB", 4 << 10, 1 << 20)):
+        specs = _batch_specs(si, 1, 64, lo, hi, R)
+        recvs = []
+        for coll, dt, n in specs:
+            rl = n * R if coll == "allgather" else n
+            recvs.append([torch.empty(rl * ELEM[dt], dtype=torch.uint8, device="cuda") for _ in range(R)])
+
+        def issue(group):
+            if group:
+                vccl.vcclGroupStart()
+            for k, (coll, dt, n) in enumerate(specs):
+                for r in range(R):
+                    s, d = arenas[dt][r], recvs[k][r]
+                    if coll == "allreduce":
+                        vccl.vcclAllReduce(s, d, n, codes[dt], vccl.vcclSum, comms[r], stream)
+                    elif coll == "allgather":
+                        vccl.vcclAllGather(s, d, n, codes[dt], comms[r], stream)
+                    else:
+                        vccl.vcclReduceScatter(s, d, n, codes[dt], vccl.vcclSum, comms[r], stream)
+            if group:
+                vccl.vcclGroupEnd()
+
+        def timed(group):
+            issue(group)
+            torch.cuda.synchronize()
+            dev, wall = [], []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                t0 = time.perf_counter()
+                e0.record(stream)
+                issue(group)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                wall.append(time.perf_counter() - t0)
+                dev.append(e0.elapsed_time(e1) / 1e3)
+            return float(np.median(dev)), float(np.median(wall))
+
+        pc_dev, pc_wall = timed(False)
+        snap = [[x.clone() for x in rr] for rr in recvs]
+        for rr in recvs:
+            for x in rr:
+                x.fill_(0x5A)
+        g_dev, g_wall = timed(True)
+        plan = vccl.vcclCommGetLastPlan(comms[0])
+        same = all(bool(torch.equal(a, b)) for ra, rb in zip(snap, recvs) for a, b in zip(ra, rb))
+        err = vccl.vcclCommGetAsyncError(comms[0])
+        if err != vccl.vcclSuccess:
+            raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)} in grouped leg")
+        sizes = [n * ELEM[dt] * (R if c != "allreduce" else 1) for c, dt, n in specs]
+        result[name] = {"ncolls": len(specs), "bytes_total": int(sum(sizes)),
+                        "sub_1MiB_fraction": round(float(np.mean([x < (1 << 20) for x in sizes])), 3),
+                        "grouped_ms": round(g_dev * 1e3, 4), "per_call_ms": round(pc_dev * 1e3, 4),
+                        "grouped_wall_ms": round(g_wall * 1e3, 4), "per_call_wall_ms": round(pc_wall * 1e3, 4),
+                        "speedup": round(pc_dev / g_dev, 3), "lanes": plan["nlanes"],
+                        "grouped_equals_per_call": same}
+        del recvs, snap
+    return result
+
+
+def serving_leg(vccl, torch, si, R, rates, nreq, nwarm, lanes=32, budget=4 << 30):
+    """Poisson request streams through the continuous-batching server."""
+    import numpy as np
+    arena = 128 << 20
+    arenas = _send_arenas(torch, si, si.WL_SERVING, R, arena)
+    recv = [torch.empty(arena, dtype=torch.uint8, device="cuda") for _ in range(R)]
+    base_s = {dt: [t.data_ptr() for t in arenas[dt]] for dt in DTYPES}
+    base_r = [t.data_ptr() for t in recv]
+    codes = {"float32": vccl.vcclFloat32, "bfloat16": vccl.vcclBfloat16, "int32": vccl.vcclInt32}
+    comms = vccl.vcclCommInitAll(R)
+    torch.cuda.synchronize()
+    srv = vccl.vcclServeCreate(comms, budget, lanes)
+    out = {"lanes": lanes, "budget_bytes": budget, "requests_per_rate": nreq, "warmup_per_rate": nwarm,
+           "rates": []}
+    try:
+        for k, lam in enumerate(rates):
+            rng = si.rng_for(si.WL_SERVING, 0, 100 + k)
+            total = nreq + nwarm
+            sizes = si.log_uniform_sizes(rng, total, 1 << 10, 128 << 20)
+            reqs, nbytes = [], 0
+            for i in range(total):
+                u = rng.uniform()
+                coll = "allreduce" if u < 0.6 else ("allgather" if u < 0.8 else "reducescatter")
+                dt = DTYPES[int(rng.integers(0, 3))]
+                E = ELEM[dt]
+                n = max(1, int(sizes[i]) // E // (R if coll != "allreduce" else 1))
+                span_s = n * E * (R if coll == "reducescatter" else 1)
+                span_r = n * E * (R if coll == "allgather" else 1)
+                off_s = int(rng.integers(0, (arena - span_s) // 16 + 1)) * 16
+                off_r = int(rng.integers(0, (arena - span_r) // 16 + 1)) * 16
+                reqs.append(vccl.make_request(COLL_CODES[coll], codes[dt], vccl.vcclSum, 0, n,
+                                              [b + off_s for b in base_s[dt]], [b + off_r for b in base_r]))
+                nbytes += int(sizes[i])
+            arr = si.poisson_arrivals(rng, total, lam)
+            lat, st = vccl.vcclServeReplay(srv, reqs, (arr * 1e9).astype(np.int64))
+            if any(x != vccl.vcclSuccess for x in st):
+                raise RuntimeError("serving: a request failed")
+            lat = np.asarray(lat[nwarm:], dtype=np.float64) / 1e3
+            done = arr[nwarm:] + lat / 1e6
+            span = float(done.max() - arr[nwarm])
+            out["rates"].append({"offered_per_s": lam, "achieved_per_s": round(nreq / span, 1),
+                                 "p50_us": round(float(np.percentile(lat, 50)), 1),
+                                 "p99_us": round(float(np.percentile(lat, 99)), 1),
+                                 "mean_bytes": int(nbytes / total)})
+    finally:
+        vccl.vcclServeDestroy(srv)
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +233,12 @@ def main():
     ap.add_argument("--nranks", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-protocols", action="store_true")
+    ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="requests per rate before measurement")
+    ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000,100000")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 counter runs: 3 plain 1 GiB device copies (calibration), "
                          "then `steps` AllReduces of the workload; prints nothing else")
@@ -171,7 +340,7 @@ def main():
     if not args.no_cpu:
         from oracle import simulate as sim
         reps, t_cpu, t0 = 0, 0.0, time.perf_counter()
-        while reps < 2 or (time.perf_counter() - t0 < 10.0 and reps < 50):
+        while reps < 2 or time.perf_counter() - t0 < args.cpu_seconds:
             t1 = time.perf_counter()
             sim.run("allreduce", xs, dtype="float32", nchannels=plan["nchannels"], chunk_bytes=plan["chunkBytes"])
             t_cpu += time.perf_counter() - t1
@@ -181,8 +350,16 @@ def main():
                "sample": f"the full workload ({R} ranks x {args.size_mib} MiB fp32, same plan), {reps} repetitions, "
                          f"{t_cpu:.1f} s total, numpy single-threaded"}
 
+    grouped = None
+    if not args.no_grouped:
+        grouped = grouped_leg(vccl, torch, si, comms, stream)
     for c in comms:
         vccl.vcclCommDestroy(c)
+    del sends, recvs
+    serving = None
+    if not args.no_serving:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        serving = serving_leg(vccl, torch, si, R, rates, args.serve_requests, args.serve_warmup)
 
     out = {
         "metric": METRIC,
@@ -210,6 +387,8 @@ def main():
                      "kernel": "vccl::collKernel", "alg_bytes_per_launch": abytes,
                      "avg_launch_ms": round(ev_step * 1e3, 4)},
         "protocols": protos,
+        "grouped": grouped,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -312,7 +312,7 @@ vcclResult_t vcclServeReplay(vcclServer_t s, const vcclRequest_t* reqs, const ui
                              uint64_t* latency_ns, vcclResult_t* statuses) {
   if (!s || !reqs || !arrival_ns || !latency_ns || n < 0) return vcclInvalidArgument;
   std::vector<uint64_t> ids(n, 0), tArr(n, 0);
-  std::vector<char> fin(n, 0);
+  std::vector<int> pending;  // submitted, not yet seen complete
   int next = 0, finished = 0;
   const uint64_t t0 = nowNs();
   while (finished < n) {
@@ -321,19 +321,24 @@ vcclResult_t vcclServeReplay(vcclServer_t s, const vcclRequest_t* reqs, const ui
       tArr[next] = t0 + arrival_ns[next];
       vcclResult_t r = vcclServeSubmit(s, &reqs[next], &ids[next]);
       if (r != vcclSuccess) return r;
+      pending.push_back(next);
       ++next;
     }
     vcclResult_t r = progress(s);
     if (r != vcclSuccess) return r;
-    for (int i = 0; i < next; ++i) {
-      if (fin[i]) continue;
+    for (size_t k = 0; k < pending.size();) {
+      const int i = pending[k];
       auto it = s->reqs.find(ids[i]);
-      if (it == s->reqs.end() || it->second->state != 2) continue;
+      if (it == s->reqs.end() || it->second->state != 2) {
+        ++k;
+        continue;
+      }
       latency_ns[i] = it->second->tDone - tArr[i];
       if (statuses) statuses[i] = it->second->status;
       delete it->second;
       s->reqs.erase(it);
-      fin[i] = 1;
+      pending[k] = pending.back();
+      pending.pop_back();
       ++finished;
     }
   }
