@@ -10,6 +10,8 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
               duration (HIP events on the launch stream over the timed
               region) against the 8 TB/s HBM3E peak
   protocols   the same AllReduce forced to each protocol (busBW, HBM fraction)
+  collectives_r16  every collective (and the tree AllReduce) at 16 ranks, bf16,
+              64 MiB per rank: busBW and HBM fraction
   grouped     64 mixed collectives (AR/AG/RS, 4 KiB..16 MiB log-uniform, fp32 /
               bf16 / int32) in one GroupStart/GroupEnd launch against one
               launch per collective, and the same for a batch of sub-1 MiB
@@ -21,6 +23,7 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib 64]
                        [--no-cpu] [--no-protocols] [--no-grouped] [--no-serving]
+                       [--no-collectives]
 """
 from __future__ import annotations
 
@@ -103,6 +106,86 @@ def _batch_specs(si, seed, count, lo, hi, R):
         n = max(1, int(sizes[i]) // E // (R if coll != "allreduce" else 1))
         specs.append((coll, dt, n))
     return specs
+
+
+def coll_alg_bytes(coll, plan, R, size):
+    """Algorithmic bytes of one launch (FIFO traffic included; f = 1 / 2 /
+    16/15 for Simple / LL / LL128).  size = the larger per-rank buffer.
+    AllReduce as alg_bytes_per_launch; ReduceScatter / AllGather with block
+    b = size / R: R [R + 1 + 2f(R-1)] b, or R (2R - 1) b for a direct
+    AllGather; Broadcast / Reduce: [R + 1 + 2f(R-1)] size, or (2R - 1) size
+    for a direct Broadcast."""
+    f = {0: 1.0, 1: 2.0, 2: 16.0 / 15.0}[plan["proto"]]
+    direct = plan["proto"] == 0 and plan["direct"]
+    if coll == "allreduce":
+        return alg_bytes_per_launch(plan, R, size)
+    if coll in ("reducescatter", "allgather"):
+        b = size / R
+        if coll == "allgather" and direct:
+            return R * (2 * R - 1) * b
+        return R * (R + 1 + 2 * f * (R - 1)) * b
+    if coll == "broadcast" and direct:
+        return (2 * R - 1) * size
+    return (R + 1 + 2 * f * (R - 1)) * size
+
+
+def collectives_leg(vccl, torch, si, R=16, size=64 << 20, steps=10):
+    """Every collective at one size: 16 ranks, bf16 U(-1,1), sum (the tree /
+    chain workload), tuner plans plus the tree forced for AllReduce."""
+    arenas = _send_arenas(torch, si, si.WL_TREE_AND_CHAINS, R, size)["bfloat16"]
+    recvs = [torch.empty(size, dtype=torch.uint8, device="cuda") for _ in range(R)]
+    comms = vccl.vcclCommInitAll(R)
+    stream = torch.cuda.current_stream()
+    bf = vccl.vcclBfloat16
+    bus = {"allreduce": 2 * (R - 1) / R, "reducescatter": (R - 1) / R, "allgather": (R - 1) / R,
+           "broadcast": 1.0, "reduce": 1.0}
+    out = {"nranks": R, "bytes_per_rank": size, "dtype": "bf16", "op": "sum"}
+    try:
+        for name, coll, algo in (("allreduce", "allreduce", -1), ("allreduce_tree", "allreduce", 1),
+                                 ("reducescatter", "reducescatter", -1), ("allgather", "allgather", -1),
+                                 ("broadcast", "broadcast", -1), ("reduce", "reduce", -1)):
+            vccl.vcclCommSetTuning(comms[0], algo=algo)
+            n = size // 2 // (R if coll in ("allgather", "reducescatter") else 1)
+
+            def issue():
+                for r in range(R):
+                    s, d = arenas[r], recvs[r]
+                    if coll == "allreduce":
+                        vccl.vcclAllReduce(s, d, n, bf, vccl.vcclSum, comms[r], stream)
+                    elif coll == "reducescatter":
+                        vccl.vcclReduceScatter(s, d, n, bf, vccl.vcclSum, comms[r], stream)
+                    elif coll == "allgather":
+                        vccl.vcclAllGather(s, d, n, bf, comms[r], stream)
+                    elif coll == "broadcast":
+                        vccl.vcclBroadcast(s, d, n, bf, 0, comms[r], stream)
+                    else:
+                        vccl.vcclReduce(s, d, n, bf, vccl.vcclSum, 0, comms[r], stream)
+
+            for _ in range(2):
+                issue()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                issue()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / steps
+            err = vccl.vcclCommGetAsyncError(comms[0])
+            if err != vccl.vcclSuccess:
+                raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)} in {name}")
+            plan = vccl.vcclCommGetLastPlan(comms[0])
+            ab = coll_alg_bytes(coll, plan, R, size)
+            out[name] = {"ms": round(t * 1e3, 4), "busbw_gbs": round(size / t / 1e9 * bus[coll], 2),
+                         "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
+                         "algo": ["ring", "tree"][plan["algo"]], "proto": ["simple", "ll", "ll128"][plan["proto"]],
+                         "nchannels": plan["nchannels"], "direct": plan["direct"]}
+    finally:
+        vccl.vcclCommSetTuning(comms[0])
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+    return out
 
 
 def grouped_leg(vccl, torch, si, comms, stream, reps=10):
@@ -235,6 +318,7 @@ def main():
     ap.add_argument("--no-protocols", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-collectives", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=200, help="requests per rate before measurement")
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000,100000")
@@ -356,6 +440,9 @@ def main():
     for c in comms:
         vccl.vcclCommDestroy(c)
     del sends, recvs
+    colls16 = None
+    if not args.no_collectives:
+        colls16 = collectives_leg(vccl, torch, si)
     serving = None
     if not args.no_serving:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
@@ -387,6 +474,7 @@ def main():
                      "kernel": "vccl::collKernel", "alg_bytes_per_launch": abytes,
                      "avg_launch_ms": round(ev_step * 1e3, 4)},
         "protocols": protos,
+        "collectives_r16": colls16,
         "grouped": grouped,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -209,7 +209,14 @@ vcclResult_t vcclProbeXccIds(int n, int* ids);
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching over one persistent kernel: requests are admitted
- * while earlier ones still run, as lanes and the staging budget free up. */
+ * while earlier ones still run, as lanes and the staging budget free up.
+ * Admission takes the oldest request that fits; a request that does not fit
+ * yet lets younger ones pass for at most VCCL_SERVE_BYPASS_US microseconds
+ * (default 500), after which nothing overtakes it.  A request's plan is the
+ * per-call planner's for the same arguments, with at most
+ * VCCL_SERVE_MAX_LANES_PER_REQUEST lanes (default half the server's), so it
+ * depends only on the request and a request gives the same result alone and
+ * among others. */
 typedef struct vcclServer* vcclServer_t;
 
 typedef struct {
@@ -239,10 +246,14 @@ vcclResult_t vcclServeTest(vcclServer_t server, uint64_t id, int* done, vcclResu
  * per-request result.  Host arrays of n entries, caller-owned. */
 vcclResult_t vcclServeReplay(vcclServer_t server, const vcclRequest_t* reqs, const uint64_t* arrival_ns, int n,
                              uint64_t* latency_ns, vcclResult_t* statuses);
-/* Monitoring: for each of the first maxEntries (lane, rank) pairs, 5 words
- * into out[]: requests posted to the lane (host), the last posted count the
- * device observed, entries it picked up, entries it completed, and its poll
- * iteration count.  Reads host memory only. */
+/* Monitoring: for each of the first maxEntries (lane, rank) pairs,
+ * VCCL_SERVE_DEBUG_WORDS words into out[]: requests posted to the lane (host),
+ * the last posted count the workgroup observed (the lane's rank-0 workgroup
+ * watches the host counter, the others its release counter), entries it
+ * picked up, entries it completed, its poll iteration count, and the device
+ * clock (100 MHz ticks) when it picked up and finished its last entry.
+ * Reads host memory only. */
+#define VCCL_SERVE_DEBUG_WORDS 7
 vcclResult_t vcclServeDebugState(vcclServer_t server, uint64_t* out, int maxEntries);
 /* Drains every request, stops the persistent kernel and frees. */
 vcclResult_t vcclServeDestroy(vcclServer_t server);

@@ -319,10 +319,15 @@ def vcclServeReplay(server, requests, arrival_ns):
     return list(lat), list(st)
 
 
+VCCL_SERVE_DEBUG_WORDS = 7
+
+
 def vcclServeDebugState(server, entries: int):
-    arr = (C.c_uint64 * (5 * entries))()
+    """Per (lane, rank): [posted, seen, picked, done, polls, pickup_tick, finish_tick]."""
+    w = VCCL_SERVE_DEBUG_WORDS
+    arr = (C.c_uint64 * (w * entries))()
     _check(_lib.vcclServeDebugState(server, arr, int(entries)), "vcclServeDebugState")
-    return [list(arr[5 * k:5 * k + 5]) for k in range(entries)]
+    return [list(arr[w * k:w * k + w]) for k in range(entries)]
 
 
 def vcclServeDestroy(server):

@@ -1110,29 +1110,34 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
   c.lid = threadIdx.x & 63;
   c.sAbort = &sAbort;
   if (threadIdx.x == 0) sAbort = 0;
+  const bool leader = rank == 0;
+  uint64_t* dbg = d.dbg + ((uint64_t)lane * R + rank) * SERVE_STRIDE_U64;
+  uint64_t* laneSeq = d.laneSeq + (uint64_t)lane * SERVE_STRIDE_U64;
   uint64_t seq = d.startSeq[lane];
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) {
+      // wait for entry `seq`: the leader watches the host's posted counter,
+      // the others the leader's release counter in device memory
       int cmd = 0;
       const uint64_t t0 = nowTicks();
-      uint64_t* dbg = d.dbg + ((uint64_t)lane * R + rank) * SERVE_STRIDE_U64;
       for (uint32_t it = 0;; ++it) {
-        const uint64_t p = ldSystem64(d.posted + (uint64_t)lane * SERVE_STRIDE_U64);
+        const uint64_t p = leader ? ldSystem64(d.posted + (uint64_t)lane * SERVE_STRIDE_U64) : ldAgent(laneSeq);
         if ((it & 1023u) == 0) {
           __hip_atomic_store(dbg, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           __hip_atomic_store(dbg + 2, (uint64_t)it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
         if (p > seq) {
           cmd = 1;
-          __hip_atomic_store(dbg + 1, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           break;
         }
-        if (ldSystem32(d.stop)) break;
-        __builtin_amdgcn_s_sleep(2);
+        // back off once the lane has been idle for a while (~100 us)
+        if (it < 2048u) __builtin_amdgcn_s_sleep(2);
+        else __builtin_amdgcn_s_sleep(16);
         if ((it & 63u) == 63u) {
+          if (ldSystem32(d.stop)) break;
           if (ldSystem32(d.comm->abortFlag)) break;
-          if (nowTicks() - t0 > d.idleTicks) {
+          if (leader && nowTicks() - t0 > d.idleTicks) {
             // the whole kernel stops together (a lane whose workgroups left
             // could not run the work the host posts next); the host relaunches
             // it when work arrives
@@ -1141,22 +1146,48 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
           }
         }
       }
+      if (cmd) {
+        __hip_atomic_store(dbg + 1, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(dbg + 3, nowTicks(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
       sCmd = cmd;
     }
     __syncthreads();
     if (sCmd != 1) break;
-    const ServeEntry* e = d.queue + (uint64_t)lane * SERVE_QUEUE + seq % SERVE_QUEUE;
-    if (threadIdx.x < sizeof(WorkItem) / 4)
-      ((uint32_t*)&sItem)[threadIdx.x] = __hip_atomic_load(((const uint32_t*)&e->item) + threadIdx.x,
-                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    if (threadIdx.x < sizeof(CollArgs) / 8)
-      ((uint64_t*)&sArgs)[threadIdx.x] = ldSystem64(((const uint64_t*)&e->args) + threadIdx.x);
+    const uint64_t slot = (uint64_t)lane * SERVE_QUEUE + seq % SERVE_QUEUE;
+    constexpr uint32_t kItemWords = sizeof(WorkItem) / 4, kArgWords = sizeof(CollArgs) / 8;
+    if (leader) {
+      // host entry -> LDS and the device mirror, then release the lane
+      const ServeEntry* e = d.queue + slot;
+      ServeEntry* m = d.mirror + slot;
+      if (threadIdx.x < kItemWords) {
+        const uint32_t w = __hip_atomic_load(((const uint32_t*)&e->item) + threadIdx.x, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_SYSTEM);
+        ((uint32_t*)&sItem)[threadIdx.x] = w;
+        __hip_atomic_store(((uint32_t*)&m->item) + threadIdx.x, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (threadIdx.x < kArgWords) {
+        const uint64_t w = ldSystem64(((const uint64_t*)&e->args) + threadIdx.x);
+        ((uint64_t*)&sArgs)[threadIdx.x] = w;
+        stAgent(((uint64_t*)&m->args) + threadIdx.x, w);
+      }
+      drainVmem();
+      __syncthreads();
+      if (threadIdx.x == 0) stAgent(laneSeq, seq + 1);
+    } else {
+      const ServeEntry* m = d.mirror + slot;
+      if (threadIdx.x < kItemWords)
+        ((uint32_t*)&sItem)[threadIdx.x] =
+            __hip_atomic_load(((const uint32_t*)&m->item) + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (threadIdx.x < kArgWords) ((uint64_t*)&sArgs)[threadIdx.x] = ldAgent(((const uint64_t*)&m->args) + threadIdx.x);
+    }
     __syncthreads();
     dispatchItem(c, sItem, sArgs, sSteps);
     drainVmem();
     __syncthreads();
     if (*(volatile int*)&sAbort) break;
     if (threadIdx.x == 0) {
+      __hip_atomic_store(dbg + 4, nowTicks(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
       // outputs visible to the host and to later kernels before completion
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
       __hip_atomic_store(d.done + ((uint64_t)lane * R + rank) * SERVE_STRIDE_U64, seq + 1, __ATOMIC_RELAXED,

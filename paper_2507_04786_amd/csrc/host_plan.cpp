@@ -37,6 +37,35 @@ static uint64_t maxChunkBytes(const Clique* c, int proto) {
   return (uint64_t)(SLOT_BYTES_LL128 / LL128_LINE) * LL128_DATA;
 }
 
+// Measured plan table: for each (ranks, collective, log2 of the per-rank
+// size) the fastest (algorithm, protocol, channels) of a sweep over all of
+// them on this chip (fewest channels among plans within 10 % of the best).
+struct TuneEntry {
+  int nranks, coll, log2, algo, proto, nchannels;
+  float us;
+};
+static const TuneEntry kTuneTable[] = {
+#include "tune_table.inc"
+};
+
+// Entry for the measured rank count nearest to R (4, 8 or 16) and the size
+// bucket nearest to S on a log scale.
+static const TuneEntry* tuneLookup(int R, uint8_t coll, uint64_t S) {
+  const int tr = R <= 5 ? 4 : (R <= 11 ? 8 : 16);
+  const int lg = S <= 8 ? 3 : (int)std::lround(std::log2((double)S));
+  const TuneEntry* best = nullptr;
+  int bestDist = 1 << 30;
+  for (const TuneEntry& e : kTuneTable) {
+    if (e.nranks != tr || e.coll != coll) continue;
+    const int dist = std::abs(e.log2 - lg);
+    if (dist < bestDist) {
+      bestDist = dist;
+      best = &e;
+    }
+  }
+  return best;
+}
+
 void channelRange(uint64_t n, int nchannels, uint64_t align, int ch, uint64_t* start, uint64_t* count) {
   const uint64_t per = n ? roundUp(ceilDiv(n, (uint64_t)nchannels), align) : 0;
   const uint64_t s = std::min(n, (uint64_t)ch * per);
@@ -51,27 +80,23 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   auto pick = [&](int api, int env, int dflt) { return api >= 0 ? api : (env >= 0 ? env : dflt); };
   auto pickPos = [&](long api, long env, long dflt) { return api > 0 ? api : (env > 0 ? env : dflt); };
 
-  // --- algorithm (Tree exists for AllReduce only)
-  int algo = pick(c->apiTune.algo, c->envTune.algo, ALGO_RING);
-  if (algo == ALGO_TREE && coll.coll != COLL_ALLREDUCE) {
-    if (c->apiTune.algo == ALGO_TREE || (c->apiTune.algo < 0 && c->envTune.algo == ALGO_TREE)) {
-      // a forced tree applies to AllReduce; other collectives have only the ring
-      algo = ALGO_RING;
-    }
-  }
-  // --- protocol: small -> LL, large -> Simple (measured crossover near 1 MiB
-  // per rank for 8 ranks)
-  int dfltProto = S <= (1u << 20) ? PROTO_LL : PROTO_SIMPLE;
+  // --- defaults from the measured table (Section III-D: LL / LL128 for small
+  // messages, Simple for large ones; Section V-F: tree for small AllReduce,
+  // ring for large)
+  const TuneEntry* te = tuneLookup(R, coll.coll, S);
+  int dfltAlgo = te ? te->algo : ALGO_RING;
+  if (coll.coll != COLL_ALLREDUCE || R < 4) dfltAlgo = ALGO_RING;
+  const int dfltProto = te ? te->proto : (S <= (1u << 20) ? PROTO_LL : PROTO_SIMPLE);
+  // --- algorithm (Tree exists for AllReduce only; a forced tree elsewhere
+  // falls back to the ring)
+  int algo = pick(c->apiTune.algo, c->envTune.algo, dfltAlgo);
+  if (algo == ALGO_TREE && coll.coll != COLL_ALLREDUCE) algo = ALGO_RING;
   int proto = pick(c->apiTune.proto, c->envTune.proto, dfltProto);
-  // tree AllReduce: 2 log2(R) hops instead of 2R - 1, so it wins on latency
-  if (c->apiTune.algo < 0 && c->envTune.algo < 0 && coll.coll == COLL_ALLREDUCE && R >= 4 && S <= 64 * 1024)
-    algo = ALGO_TREE;
-  // --- channels: one workgroup per CU at most (R * C <= 256), and enough
-  // bytes per channel to amortise the per-step synchronisation
-  const uint64_t perCh = proto == PROTO_SIMPLE ? 512 * 1024 : 16 * 1024;
-  // up to two workgroups per CU: while one waits on a flag the other moves data
+  // --- channels: up to two workgroups per CU (while one waits on a flag the
+  // other moves data)
   const int laneCap = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
-  long dfltC = (long)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)laneCap, S / perCh));
+  long dfltC = te ? te->nchannels : (long)std::max<uint64_t>(1, std::min<uint64_t>(laneCap, S / (512 * 1024)));
+  dfltC = std::max(1L, std::min<long>(dfltC, laneCap));
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));
   // --- workgroup size

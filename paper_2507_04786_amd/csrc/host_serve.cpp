@@ -1,9 +1,10 @@
 // Serving: continuous batching over one persistent kernel.
 //
-// Requests are admitted in arrival order as soon as enough lanes are free and
-// the in-flight bytes (request buffers plus the FIFOs of the lanes they hold)
-// fit the budget; requests admitted while others run execute concurrently on
-// their own lanes.  The plan of a request (protocol, channels, chunk) depends
+// Requests are admitted oldest first as soon as enough lanes are free and the
+// in-flight bytes (request buffers plus the FIFOs of the lanes they hold) fit
+// the budget; a request that does not fit lets younger ones pass for a bounded
+// time.  Requests admitted while others run execute concurrently on their own
+// lanes.  The plan of a request (protocol, channels, chunk) depends
 // only on the request, never on the load, so a request gives the same bits
 // alone and in a mix.
 #include <time.h>
@@ -47,6 +48,8 @@ struct vcclServer {
   int L = 0;
   int block = 512;
   size_t budget = 0, used = 0;
+  int maxLanesPerReq = 1;
+  uint64_t bypassNs = 0;
   hipStream_t stream = nullptr;
   ServeDesc desc{};
   int grid = 0;
@@ -56,6 +59,8 @@ struct vcclServer {
   uint64_t* hDone = nullptr;
   uint32_t* hStop = nullptr;
   uint64_t* hDbg = nullptr;
+  ServeEntry* dMirror = nullptr;
+  uint64_t* dLaneSeq = nullptr;
   uint64_t posted[MAX_LANES] = {0};
   bool laneBusy[MAX_LANES] = {false};
   std::deque<Req*> waiting;
@@ -130,13 +135,21 @@ vcclResult_t progress(vcclServer* s) {
     }
     return vcclSuccess;
   }
+  // Admission: oldest first.  A request that does not fit yet (lanes or
+  // budget) lets younger ones that fit go ahead until it has waited
+  // bypassNs; from then on nothing overtakes it, so it cannot starve.
   bool admitted = false;
-  while (!s->waiting.empty()) {
-    Req* q = s->waiting.front();
-    int freeLanes = 0;
-    for (int l = 0; l < s->L; ++l) freeLanes += s->laneBusy[l] ? 0 : 1;
-    if (freeLanes < q->plan.nchannels || s->used + q->bytes > s->budget) break;  // strict arrival order
-    s->waiting.pop_front();
+  int freeLanes = 0;
+  for (int l = 0; l < s->L; ++l) freeLanes += s->laneBusy[l] ? 0 : 1;
+  const uint64_t now = nowNs();
+  for (auto wi = s->waiting.begin(); wi != s->waiting.end() && freeLanes > 0;) {
+    Req* q = *wi;
+    if (freeLanes < q->plan.nchannels || s->used + q->bytes > s->budget) {
+      if (now - q->tSubmit >= s->bypassNs) break;
+      ++wi;
+      continue;
+    }
+    wi = s->waiting.erase(wi);
     Coll coll{};
     coll.coll = (uint8_t)q->r.coll;
     coll.dtype = q->r.datatype;
@@ -168,6 +181,7 @@ vcclResult_t progress(vcclServer* s) {
       __atomic_store_n(s->hPosted + (uint64_t)l * SERVE_STRIDE_U64, s->posted[l], __ATOMIC_RELEASE);
     }
     s->used += q->bytes;
+    freeLanes -= q->nlanes;
     q->state = 1;
     s->inflight.push_back(q);
     admitted = true;
@@ -198,6 +212,11 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   s->L = lanes;
   s->budget = budgetBytes;
   s->block = (int)envLong("VCCL_SERVE_NTHREADS", 512);
+  // one request takes at most half the lanes (fewer lanes per request use the
+  // device more efficiently and let two large requests overlap)
+  s->maxLanesPerReq = (int)std::max(1L, std::min<long>(lanes, envLong("VCCL_SERVE_MAX_LANES_PER_REQUEST",
+                                                                      std::max(1, lanes / 2))));
+  s->bypassNs = (uint64_t)envLong("VCCL_SERVE_BYPASS_US", 500) * 1000ull;
   int occ = 0;
   if (vcclServeOccupancy(s->block, &occ) != hipSuccess || occ < 1) {
     delete s;
@@ -217,6 +236,10 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   if (e == hipSuccess) e = hipHostMalloc((void**)&s->hStop, 256, hipHostMallocCoherent);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&s->hDbg, sizeof(uint64_t) * SERVE_STRIDE_U64 * MAX_LANES * MAX_RANKS, hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->dMirror, sizeof(ServeEntry) * lanes * SERVE_QUEUE);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->dLaneSeq, sizeof(uint64_t) * SERVE_STRIDE_U64 * lanes);
+  if (e == hipSuccess) e = hipMemset(s->dLaneSeq, 0, sizeof(uint64_t) * SERVE_STRIDE_U64 * lanes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     logError("serve create", e, __FILE__, __LINE__);
     return vcclUnhandledHipError;
@@ -232,6 +255,8 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   s->desc.stop = s->hStop;
   memset(s->hDbg, 0, sizeof(uint64_t) * SERVE_STRIDE_U64 * MAX_LANES * MAX_RANKS);
   s->desc.dbg = s->hDbg;
+  s->desc.mirror = s->dMirror;
+  s->desc.laneSeq = s->dLaneSeq;
   s->desc.idleTicks = (uint64_t)((double)envLong("VCCL_SERVE_IDLE_US", 1000000) * c->ticksPerUs);
   s->desc.nlanes = (uint32_t)lanes;
   s->desc.nranks = (uint32_t)R;
@@ -277,7 +302,7 @@ vcclResult_t vcclServeSubmit(vcclServer_t s, const vcclRequest_t* req, uint64_t*
     delete q;
     return r;
   }
-  q->plan.nchannels = std::min(q->plan.nchannels, s->L);
+  q->plan.nchannels = std::min(q->plan.nchannels, s->maxLanesPerReq);
   q->bytes = requestBytes(c, *req, q->plan);
   if (q->bytes > s->budget) {
     delete q;
@@ -346,7 +371,8 @@ vcclResult_t vcclServeReplay(vcclServer_t s, const vcclRequest_t* reqs, const ui
 }
 
 // Debug view: for every (lane, rank): posted (host), last posted value the
-// device saw, items the device picked up, done (device), poll iterations.
+// device saw, items the device picked up, done (device), poll iterations, and
+// the device clock (100 MHz) when the last item was picked up and finished.
 vcclResult_t vcclServeDebugState(vcclServer_t s, uint64_t* out, int maxEntries) {
   if (!s || !out) return vcclInvalidArgument;
   const int R = s->c->nranks;
@@ -354,11 +380,14 @@ vcclResult_t vcclServeDebugState(vcclServer_t s, uint64_t* out, int maxEntries) 
   for (int l = 0; l < s->L; ++l)
     for (int r = 0; r < R && k < maxEntries; ++r, ++k) {
       const uint64_t* d = s->hDbg + ((uint64_t)l * R + r) * SERVE_STRIDE_U64;
-      out[5 * k + 0] = __atomic_load_n(s->hPosted + (uint64_t)l * SERVE_STRIDE_U64, __ATOMIC_ACQUIRE);
-      out[5 * k + 1] = __atomic_load_n(d, __ATOMIC_ACQUIRE);
-      out[5 * k + 2] = __atomic_load_n(d + 1, __ATOMIC_ACQUIRE);
-      out[5 * k + 3] = __atomic_load_n(s->hDone + ((uint64_t)l * R + r) * SERVE_STRIDE_U64, __ATOMIC_ACQUIRE);
-      out[5 * k + 4] = __atomic_load_n(d + 2, __ATOMIC_ACQUIRE);
+      uint64_t* o = out + (uint64_t)VCCL_SERVE_DEBUG_WORDS * k;
+      o[0] = __atomic_load_n(s->hPosted + (uint64_t)l * SERVE_STRIDE_U64, __ATOMIC_ACQUIRE);
+      o[1] = __atomic_load_n(d, __ATOMIC_ACQUIRE);
+      o[2] = __atomic_load_n(d + 1, __ATOMIC_ACQUIRE);
+      o[3] = __atomic_load_n(s->hDone + ((uint64_t)l * R + r) * SERVE_STRIDE_U64, __ATOMIC_ACQUIRE);
+      o[4] = __atomic_load_n(d + 2, __ATOMIC_ACQUIRE);
+      o[5] = __atomic_load_n(d + 3, __ATOMIC_ACQUIRE);
+      o[6] = __atomic_load_n(d + 4, __ATOMIC_ACQUIRE);
     }
   return vcclSuccess;
 }
@@ -378,6 +407,8 @@ vcclResult_t vcclServeDestroy(vcclServer_t s) {
   hipHostFree(s->hDone);
   hipHostFree(s->hStop);
   hipHostFree(s->hDbg);
+  hipFree(s->dMirror);
+  hipFree(s->dLaneSeq);
   c->serving = false;
   delete s;
   return vcclSuccess;

@@ -105,11 +105,16 @@ struct LaunchDesc {
 
 // ---------------------------------------------------------------- serving
 // Per-lane request queues live in pinned host memory: the host writes an
-// entry, then bumps the lane's `posted` counter; every workgroup of the lane
-// runs the entry and then publishes its own `done` counter (with a
-// system-scope release, so the outputs are visible to later work).
+// entry, then bumps the lane's `posted` counter.  Only the lane's rank-0
+// workgroup (the leader) polls host memory: it copies the entry into a
+// device-memory mirror and releases the lane's other workgroups through a
+// device counter, so host memory sees one poller per lane instead of R.
+// Every workgroup of the lane runs the entry and then publishes its own
+// `done` counter (with a system-scope release, so the outputs are visible to
+// later work).
 constexpr int SERVE_QUEUE = 4;
 constexpr int SERVE_STRIDE_U64 = 16;  // counters 128 B apart
+constexpr int SERVE_DBG_WORDS = 5;    // per (lane, rank): seen, picked, polls, pickup tick, finish tick
 
 struct ServeEntry {
   WorkItem item;
@@ -122,7 +127,9 @@ struct ServeDesc {
   uint64_t* posted;         // [nlanes] * SERVE_STRIDE_U64
   uint64_t* done;           // [nlanes * nranks] * SERVE_STRIDE_U64
   uint32_t* stop;           // set by the host to end the kernel
-  uint64_t* dbg;            // per (lane, rank): last posted value seen, items picked up, polls
+  uint64_t* dbg;            // per (lane, rank): SERVE_DBG_WORDS words, SERVE_STRIDE_U64 apart
+  ServeEntry* mirror;       // device memory: [nlanes][SERVE_QUEUE] copies made by the leaders
+  uint64_t* laneSeq;        // device memory: [nlanes] * SERVE_STRIDE_U64, entries released
   uint64_t idleTicks;       // the kernel exits after this long without work
   uint32_t nlanes, nranks, xcdMap, perXcd;
   uint64_t claimBase;

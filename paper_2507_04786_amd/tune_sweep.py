@@ -1,0 +1,158 @@
+"""Measure the plan space and write the tuner's table.
+
+Runs every collective of ``--nranks`` virtual ranks at per-rank sizes
+2^3 .. 2^28 bytes (nccl-tests convention: the larger per-rank buffer) under
+every (algorithm, protocol, channel count) the planner can choose, times each
+point with HIP events on the launch stream, and writes one JSON line per
+point.  ``--emit`` turns one or more such files into the C++ table the
+planner reads (``csrc/tune_table.inc``): for every (ranks, collective, size
+bucket) the fastest measured plan, preferring fewer channels among plans
+within 10 % of the best: a lane left free serves grouped or concurrent work,
+and a grouped launch runs every channel of a collective as its own item.
+
+Usage:
+  python paper_2507_04786_amd/tune_sweep.py --nranks 8 --out sweep_r8.jsonl
+  python paper_2507_04786_amd/tune_sweep.py --emit sweep_r4.jsonl sweep_r8.jsonl sweep_r16.jsonl
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COLLS = ("allreduce", "reducescatter", "allgather", "broadcast", "reduce")
+COLL_CODE = {"allreduce": 0, "broadcast": 1, "reduce": 2, "allgather": 3, "reducescatter": 4}
+PROTOS = ("simple", "ll", "ll128")
+CHANNELS = (1, 2, 4, 8, 16, 32)
+LOG2_MIN, LOG2_MAX = 3, 28
+SLOW_MS = 4.0   # a plan slower than this at one size is not tried at larger sizes
+TOLERANCE = 1.10  # plans this close to the fastest count as equal; the fewest channels wins
+
+
+def sweep(args):
+    sys.path.insert(0, os.path.dirname(HERE))
+    import torch
+    import paper_2507_04786_amd as vccl
+
+    R = args.nranks
+    torch.cuda.set_device(0)
+    top = 1 << args.max_log2
+    sends = [torch.empty(top // 4, dtype=torch.float32, device="cuda").normal_() for _ in range(R)]
+    recvs = [torch.empty(top // 4, dtype=torch.float32, device="cuda") for _ in range(R)]
+    stream = torch.cuda.current_stream()
+    comms = vccl.vcclCommInitAll(R)
+    out = open(args.out, "w")
+    colls = args.colls.split(",") if args.colls else COLLS
+
+    def issue(coll, n):
+        for r in range(R):
+            s, d = sends[r], recvs[r]
+            if coll == "allreduce":
+                vccl.vcclAllReduce(s, d, n, vccl.vcclFloat32, vccl.vcclSum, comms[r], stream)
+            elif coll == "reducescatter":
+                vccl.vcclReduceScatter(s, d, n, vccl.vcclFloat32, vccl.vcclSum, comms[r], stream)
+            elif coll == "allgather":
+                vccl.vcclAllGather(s, d, n, vccl.vcclFloat32, comms[r], stream)
+            elif coll == "broadcast":
+                vccl.vcclBroadcast(s, d, n, vccl.vcclFloat32, 0, comms[r], stream)
+            else:
+                vccl.vcclReduce(s, d, n, vccl.vcclFloat32, vccl.vcclSum, 0, comms[r], stream)
+
+    try:
+        for coll in colls:
+            algos = ("ring", "tree") if coll == "allreduce" else ("ring",)
+            slow = set()
+            for lg in range(LOG2_MIN, args.max_log2 + 1):
+                S = 1 << lg
+                # count in elements of fp32; AG / RS: size is the larger buffer
+                n = S // 4 // (R if coll in ("allgather", "reducescatter") else 1)
+                if n < 1:
+                    continue
+                for algo in algos:
+                    for proto in PROTOS:
+                        for C in CHANNELS:
+                            key = (algo, proto, C)
+                            if key in slow:
+                                continue
+                            vccl.vcclCommSetTuning(comms[0], algo=vccl.ALGO_NAMES[algo],
+                                                   proto=vccl.PROTO_NAMES[proto], nchannels=C)
+                            issue(coll, n)
+                            torch.cuda.synchronize()
+                            plan = vccl.vcclCommGetLastPlan(comms[0])
+                            t0 = time.perf_counter()
+                            issue(coll, n)
+                            torch.cuda.synchronize()
+                            once = time.perf_counter() - t0
+                            reps = max(3, min(20, int(0.004 / max(once, 1e-6))))
+                            e0 = torch.cuda.Event(enable_timing=True)
+                            e1 = torch.cuda.Event(enable_timing=True)
+                            t0 = time.perf_counter()
+                            e0.record(stream)
+                            for _ in range(reps):
+                                issue(coll, n)
+                            e1.record(stream)
+                            torch.cuda.synchronize()
+                            wall = (time.perf_counter() - t0) / reps
+                            ms = e0.elapsed_time(e1) / reps
+                            err = vccl.vcclCommGetAsyncError(comms[0])
+                            if err != vccl.vcclSuccess:
+                                raise RuntimeError(f"device error at {coll} {S} {key}")
+                            rec = dict(R=R, coll=coll, S=S, log2=lg, algo=algo, proto=proto, C=C,
+                                       Cplan=plan["nchannels"], chunk=plan["chunkBytes"],
+                                       T=plan["nthreads"], direct=plan["direct"], ms=round(ms, 5),
+                                       wall_ms=round(wall * 1e3, 5), reps=reps)
+                            out.write(json.dumps(rec) + "\n")
+                            if ms > SLOW_MS:
+                                slow.add(key)
+                out.flush()
+                print(f"{coll} 2^{lg} done", flush=True)
+    finally:
+        vccl.vcclCommSetTuning(comms[0])
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+        out.close()
+
+
+def emit(paths, dest):
+    rows = []
+    for p in paths:
+        rows += [json.loads(line) for line in open(p) if line.strip()]
+    best = {}
+    for key in sorted({(r["R"], r["coll"], r["log2"]) for r in rows}):
+        cands = [r for r in rows if (r["R"], r["coll"], r["log2"]) == key]
+        tmin = min(r["ms"] for r in cands)
+        near = [r for r in cands if r["ms"] <= tmin * TOLERANCE]
+        pick = min(near, key=lambda r: (r["Cplan"], r["ms"]))
+        best[key] = pick
+    lines = ["// Generated by tune_sweep.py --emit from measured sweeps (fp32, sum, tuner-default",
+             "// chunk and threads); one entry per (ranks, collective, log2 of the per-rank size).",
+             "// Fields: nranks, coll, log2 bytes, algo (0 ring, 1 tree), proto (0 Simple, 1 LL,",
+             "// 2 LL128), channels, measured microseconds.",
+             f"// Sources: {', '.join(os.path.basename(p) for p in paths)}"]
+    for (R, coll, lg), r in sorted(best.items(), key=lambda kv: (kv[0][0], COLL_CODE[kv[0][1]], kv[0][2])):
+        lines.append("{%d, %d, %d, %d, %d, %d, %.1f}," % (R, COLL_CODE[coll], lg, 0 if r["algo"] == "ring" else 1,
+                                                        PROTOS.index(r["proto"]), r["Cplan"], r["ms"] * 1e3))
+    open(dest, "w").write("\n".join(lines) + "\n")
+    print(f"wrote {len(best)} entries to {dest}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nranks", type=int, default=8)
+    ap.add_argument("--out", default="sweep.jsonl")
+    ap.add_argument("--colls", default="")
+    ap.add_argument("--max-log2", type=int, default=LOG2_MAX)
+    ap.add_argument("--emit", nargs="*")
+    ap.add_argument("--dest", default=os.path.join(HERE, "csrc", "tune_table.inc"))
+    args = ap.parse_args()
+    if args.emit:
+        emit(args.emit, args.dest)
+    else:
+        sweep(args)
+
+
+if __name__ == "__main__":
+    main()
