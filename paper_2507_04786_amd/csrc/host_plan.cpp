@@ -119,7 +119,12 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   if (c->apiTune.chunkBytes) chunk = c->apiTune.chunkBytes;
   else if (c->envTune.chunkBytes) chunk = c->envTune.chunkBytes;
   else {
-    if (proto == PROTO_SIMPLE) {
+    if (proto == PROTO_SIMPLE && algo == ALGO_TREE) {
+      // a tree pipelines chunks through 2 log2(R) hops: eight chunks per
+      // channel, at most 256 KiB (measured best for large trees)
+      const uint64_t chBytes = ceilDiv(S, (uint64_t)nch);
+      chunk = std::min<uint64_t>(roundUp(std::max<uint64_t>(ceilDiv(chBytes, 8), 16 * 1024), 4096), 256 * 1024);
+    } else if (proto == PROTO_SIMPLE) {
       // a ring loop covers R chunks: take the largest chunk that still gives
       // every channel at least one full loop
       const uint64_t chBytes = ceilDiv(S, (uint64_t)nch);

@@ -151,6 +151,44 @@ def test_tree_allreduce_matrix(vccl, comms_for, proto, dtype, op):
             _assert_bits(got[r], want[r], f"tree {proto} {dtype} {op} R={R} n={n} C={C} rank {r}")
 
 
+@pytest.mark.parametrize("R", [4, 8, 16])
+def test_default_plans_match_oracle(vccl, comms_for, R):
+    """Whatever the measured tuner picks (ring or tree, any protocol, up to 32
+    channels) at sizes across the 8 B .. 2 MiB range, with ragged counts:
+    every collective against the oracle's folds for the plan it reports."""
+    comms = comms_for(R)
+    for lg in (3, 6, 10, 13, 16, 17, 18, 20, 21):
+        for coll, dtype in (("allreduce", "float32"), ("allreduce", "bfloat16"), ("reducescatter", "float32"),
+                            ("allgather", "float32"), ("broadcast", "bfloat16"), ("reduce", "float32")):
+            E = H.ELEM[dtype]
+            per = (1 << lg) // E // (R if coll in ("allgather", "reducescatter") else 1)
+            n = max(1, per - 3)
+            xs = _inputs(R, dtype, H.send_len(coll, n, R), wl=2, extra=lg * 100 + R)
+            root = R // 2 if coll in ("broadcast", "reduce") else 0
+            got = _run(vccl, comms, coll, xs, n, dtype, "sum", root)
+            plan = vccl.vcclCommGetLastPlan(comms[0])
+            what = f"default plan {plan} {coll} {dtype} R={R} n={n}"
+            if coll == "allreduce":
+                if plan["algo"] == 1:
+                    want = folds.tree_allreduce(xs, "sum", dtype, plan["nchannels"])
+                else:
+                    want = folds.ring_allreduce(xs, "sum", dtype, plan["nchannels"], plan["chunkBytes"] // E)
+                for r in range(R):
+                    _assert_bits(got[r], want, f"{what} rank {r}")
+            elif coll == "reducescatter":
+                for r in range(R):
+                    _assert_bits(got[r], folds.ring_reducescatter(xs, "sum", dtype, r), f"{what} rank {r}")
+            elif coll == "reduce":
+                _assert_bits(got[root], folds.ring_reduce(xs, "sum", dtype, root), what)
+            elif coll == "allgather":
+                want = defs.allgather(xs)
+                for r in range(R):
+                    _assert_bits(got[r], want[r], f"{what} rank {r}")
+            else:
+                for r in range(R):
+                    _assert_bits(got[r], xs[root], f"{what} rank {r}")
+
+
 @pytest.mark.parametrize("coll", ["allreduce", "allgather", "broadcast"])
 def test_direct_variants_match(vccl, comms_for, coll):
     """P2P_DIRECT-style copies give the same bits as the FIFO path."""
