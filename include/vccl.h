@@ -214,9 +214,11 @@ vcclResult_t vcclProbeXccIds(int n, int* ids);
  * yet lets younger ones pass for at most VCCL_SERVE_BYPASS_US microseconds
  * (default 500), after which nothing overtakes it.  A request's plan is the
  * per-call planner's for the same arguments, with at most
- * VCCL_SERVE_MAX_LANES_PER_REQUEST lanes (default half the server's), so it
- * depends only on the request and a request gives the same result alone and
- * among others. */
+ * VCCL_SERVE_MAX_LANES_PER_REQUEST lanes (default half the server's) unless
+ * the request holds more than half the budget (then no request of its size
+ * can run beside it and it keeps its plan's lanes, up to the server's).  The
+ * plan depends only on the request, so a request gives the same result alone
+ * and among others. */
 typedef struct vcclServer* vcclServer_t;
 
 typedef struct {

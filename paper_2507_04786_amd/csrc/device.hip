@@ -275,8 +275,11 @@ struct PtrList {
   __device__ __forceinline__ const char* get(int k) const { return k == 0 ? p0 : (k == 1 ? p1 : p2); }
 };
 
-// out[o] = in[0] (+) in[1] (+) in[2] over 16-byte vectors; every pointer 16-aligned.
-// Buffer instructions: one lane offset register shared by every stream, the
+// out[o] = in[0] (+) in[1] (+) in[2] over 16-byte vectors.  Pointers need only
+// be element-aligned: the GPU runs in unaligned-access mode, so a 16-byte
+// buffer access at any byte address moves exactly those 16 bytes (checked on
+// the device for every misalignment 0..15, loads and stores, with and without
+// sc1).  Buffer instructions: one lane offset register shared by every stream, the
 // unroll stride in a scalar offset, and hardware range checks (an access past
 // the stream's end reads zero and writes nothing), so the loop needs no
 // per-vector bounds test.
@@ -311,8 +314,8 @@ __device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, c
   }
 }
 
-// Same operation on any element-aligned pointers, 16 bytes (or the tail) per
-// lane through element-wise accesses.  Used for misaligned buffers and tails.
+// Same operation through element-wise accesses, 16 bytes (or the tail) per
+// lane: the last nbytes % 16 bytes of a step.
 template <int DT, int OP, int NIN, int NOUT, bool COH>
 __device__ __forceinline__ void reduceCopyPart(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t begin,
                                                uint64_t nbytes) {
@@ -343,15 +346,9 @@ template <int DT, int OP, int NIN, int NOUT, int SC>
 __device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
   constexpr int CP = SC == SCOPE_DEVICE ? 16 : 0;  // sc1
   constexpr bool COH = SC == SCOPE_DEVICE;
-  const uintptr_t bits = (uintptr_t)in.p0 | (uintptr_t)in.p1 | (uintptr_t)in.p2 | (uintptr_t)out.p0 |
-                         (uintptr_t)out.p1 | (uintptr_t)out.p2;
-  if ((bits & 15) == 0) {
-    const uint32_t nvec = (uint32_t)(nbytes / 16);
-    reduceCopyVec<DT, OP, NIN, NOUT, CP>(c, in, out, nvec);
-    if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT, COH>(c, in, out, (uint64_t)nvec * 16, nbytes);
-  } else {
-    reduceCopyPart<DT, OP, NIN, NOUT, COH>(c, in, out, 0, nbytes);
-  }
+  const uint32_t nvec = (uint32_t)(nbytes / 16);
+  reduceCopyVec<DT, OP, NIN, NOUT, CP>(c, in, out, nvec);
+  if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT, COH>(c, in, out, (uint64_t)nvec * 16, nbytes);
 }
 
 template <int DT, int OP, int SC>

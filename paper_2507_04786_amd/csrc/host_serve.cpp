@@ -187,7 +187,10 @@ vcclResult_t progress(vcclServer* s) {
     admitted = true;
   }
   // the kernel leaves after an idle period; bring it back when work is pending
-  if (s->running && hipStreamQuery(s->stream) == hipSuccess) s->running = false;
+  // (the kernel only ends after raising the stop word, so the runtime is
+  // asked only then)
+  if (s->running && __atomic_load_n(s->hStop, __ATOMIC_ACQUIRE) != 0 && hipStreamQuery(s->stream) == hipSuccess)
+    s->running = false;
   if (!s->running && (admitted || !s->inflight.empty())) return launchKernel(s);
   return vcclSuccess;
 }
@@ -302,8 +305,16 @@ vcclResult_t vcclServeSubmit(vcclServer_t s, const vcclRequest_t* req, uint64_t*
     delete q;
     return r;
   }
-  q->plan.nchannels = std::min(q->plan.nchannels, s->maxLanesPerReq);
+  // at most half the lanes, unless the request holds more than half the
+  // budget: then nothing of its size can run beside it and it takes the
+  // lanes its plan asks for
+  const Plan full = q->plan;
+  q->plan.nchannels = std::min(full.nchannels, s->maxLanesPerReq);
   q->bytes = requestBytes(c, *req, q->plan);
+  if (q->bytes > s->budget / 2) {
+    q->plan.nchannels = std::min(full.nchannels, s->L);
+    q->bytes = requestBytes(c, *req, q->plan);
+  }
   if (q->bytes > s->budget) {
     delete q;
     return vcclInvalidArgument;  // could never be admitted
