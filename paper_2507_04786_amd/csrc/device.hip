@@ -485,7 +485,10 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     rin[i] = makeRsrc(r[i].fifo + (r[i].step % NSLOTS) * (uint64_t)slotB, slotB);
     sout[i] = makeRsrc(s[i].fifo + (s[i].step % NSLOTS) * (uint64_t)slotB, slotB);
   }
-  const bool fast = (((uintptr_t)a.src | (uintptr_t)a.dst) & 7) == 0;
+  // user buffers: full 8-byte pieces through buffer accesses at any element
+  // alignment, the short last piece element by element
+  const __amdgpu_buffer_rsrc_t bsrc = makeRsrc(a.src, (uint32_t)a.nbytes);
+  const __amdgpu_buffer_rsrc_t bdst = makeRsrc(a.dst, (uint32_t)a.nbytes);
   const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
   bool alive = true;
   for (uint64_t p = c.tid; p < npairs; p += c.nthreads) {
@@ -494,8 +497,8 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     uint32_t acc[2] = {0, 0};
     bool have = false;
     if (a.src) {
-      if (fast && valid == 8) {
-        const uint2 v = *(const uint2*)(a.src + off);
+      if (valid == 8) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)off, 0, 0);
         acc[0] = v.x;
         acc[1] = v.y;
       } else {
@@ -527,7 +530,7 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     }
     if (!alive) break;
     if (writeDst) {
-      if (fast && valid == 8) *(uint2*)(a.dst + off) = make_uint2(acc[0], acc[1]);
+      if (valid == 8) __builtin_amdgcn_raw_buffer_store_b64(u32x2{acc[0], acc[1]}, bdst, (uint32_t)off, 0, 0);
       else storePart<E, 2>(a.dst + off, valid, acc);
     }
 #pragma unroll
@@ -559,7 +562,8 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     rin[i] = makeRsrc(r[i].fifo + (r[i].step % NSLOTS) * (uint64_t)slotB, slotB);
     sout[i] = makeRsrc(s[i].fifo + (s[i].step % NSLOTS) * (uint64_t)slotB, slotB);
   }
-  const bool fast = (((uintptr_t)a.src | (uintptr_t)a.dst) & 7) == 0;
+  const __amdgpu_buffer_rsrc_t bsrc = makeRsrc(a.src, (uint32_t)a.nbytes);
+  const __amdgpu_buffer_rsrc_t bdst = makeRsrc(a.dst, (uint32_t)a.nbytes);
   const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
   const int g = c.lid >> 3, j = c.lid & 7;
   const int plen = (j < 7) ? 16 : 8;
@@ -574,14 +578,19 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     uint32_t acc[4] = {0, 0, 0, 0};
     bool have = false;
     if (a.src) {
-      if (fast && valid == plen) {
-        const uint2 v0 = *(const uint2*)(a.src + payOff);
-        acc[0] = v0.x;
-        acc[1] = v0.y;
+      if (valid == plen) {
+        // user buffers: full pieces through buffer accesses at any element
+        // alignment, a short piece element by element
         if (plen == 16) {
-          const uint2 v1 = *(const uint2*)(a.src + payOff + 8);
-          acc[2] = v1.x;
-          acc[3] = v1.y;
+          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(bsrc, (uint32_t)payOff, 0, 0);
+          acc[0] = v.x;
+          acc[1] = v.y;
+          acc[2] = v.z;
+          acc[3] = v.w;
+        } else {
+          const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)payOff, 0, 0);
+          acc[0] = v.x;
+          acc[1] = v.y;
         }
       } else if (valid > 0) {
         loadPart<E, 4>(a.src + payOff, valid, acc);
@@ -620,9 +629,9 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     }
     if (!alive) break;
     if (writeDst && valid > 0) {
-      if (fast && valid == plen) {
-        *(uint2*)(a.dst + payOff) = make_uint2(acc[0], acc[1]);
-        if (plen == 16) *(uint2*)(a.dst + payOff + 8) = make_uint2(acc[2], acc[3]);
+      if (valid == plen) {
+        if (plen == 16) __builtin_amdgcn_raw_buffer_store_b128(u32x4{acc[0], acc[1], acc[2], acc[3]}, bdst, (uint32_t)payOff, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b64(u32x2{acc[0], acc[1]}, bdst, (uint32_t)payOff, 0, 0);
       } else {
         storePart<E, 4>(a.dst + payOff, valid, acc);
       }
