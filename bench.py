@@ -12,6 +12,7 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
   protocols   the same AllReduce forced to each protocol (busBW, HBM fraction)
   collectives_r16  every collective (and the tree AllReduce) at 16 ranks, bf16,
               64 MiB per rank: busBW and HBM fraction
+  alltoall    grouped Send/Recv between all 8 x 8 rank pairs, 64 MiB per rank
   grouped     64 mixed collectives (AR/AG/RS, 4 KiB..16 MiB log-uniform, fp32 /
               bf16 / int32) in one GroupStart/GroupEnd launch against one
               launch per collective, and the same for a batch of sub-1 MiB
@@ -186,6 +187,59 @@ def collectives_leg(vccl, torch, si, R=16, size=64 << 20, steps=10):
         for c in comms:
             vccl.vcclCommDestroy(c)
     return out
+
+
+def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):
+    """All-to-all through grouped Send/Recv: R ranks, fp32, `size` bytes per
+    rank (R blocks of size / R), one group of R * R transfers per step.
+    Algorithmic bytes: every byte is read once and written once, 2 R size."""
+    import numpy as np
+    n = size // 4 // R
+    xs = si.rank_inputs(si.WL_P2P, R, "float32", 1 << 20)
+    sends = [torch.from_numpy(x).cuda().repeat(R * n // (1 << 20)) for x in xs]
+    recvs = [torch.empty(R * n, dtype=torch.float32, device="cuda") for _ in range(R)]
+    comms = vccl.vcclCommInitAll(R)
+    stream = torch.cuda.current_stream()
+
+    def issue(ev=None):
+        vccl.vcclGroupStart()
+        for a in range(R):
+            for b in range(R):
+                vccl.vcclSend(sends[a][b * n:(b + 1) * n], n, vccl.vcclFloat32, b, comms[a], stream)
+                vccl.vcclRecv(recvs[b][a * n:(a + 1) * n], n, vccl.vcclFloat32, a, comms[b], stream)
+        if ev:
+            ev[0].record(stream)
+        vccl.vcclGroupEnd()
+        if ev:
+            ev[1].record(stream)
+
+    try:
+        for _ in range(2):
+            issue()
+        torch.cuda.synchronize()
+        # the launch's own duration: events around GroupEnd (the 2 R^2 calls
+        # before it are host work, ~0.3 ms of Python per group)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for k in range(steps):
+            issue(evs[k])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        t = float(np.median([a.elapsed_time(b) for a, b in evs])) / 1e3
+        err = vccl.vcclCommGetAsyncError(comms[0])
+        if err != vccl.vcclSuccess:
+            raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)} in all-to-all")
+        plan = vccl.vcclCommGetLastPlan(comms[0])
+        ok = all(bool(torch.equal(recvs[b][a * n:a * n + 4096], sends[a][b * n:b * n + 4096]))
+                 for a in range(R) for b in range(R))
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+    return {"nranks": R, "bytes_per_rank": size, "transfers": R * R, "ms": round(t * 1e3, 4),
+            "host_inclusive_ms": round(wall * 1e3, 4),
+            "busbw_gbs": round(size / t / 1e9 * (R - 1) / R, 2),
+            "hbm_frac": round(2 * R * size / t / 1e9 / HBM_PEAK_GBS, 4),
+            "lanes": plan["nlanes"], "items": plan["nitems"], "sampled_blocks_equal": ok}
 
 
 def grouped_leg(vccl, torch, si, comms, stream, reps=10):
@@ -441,8 +495,10 @@ def main():
         vccl.vcclCommDestroy(c)
     del sends, recvs
     colls16 = None
+    a2a = None
     if not args.no_collectives:
         colls16 = collectives_leg(vccl, torch, si)
+        a2a = alltoall_leg(vccl, torch, si)
     serving = None
     if not args.no_serving:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
@@ -475,6 +531,7 @@ def main():
                      "avg_launch_ms": round(ev_step * 1e3, 4)},
         "protocols": protos,
         "collectives_r16": colls16,
+        "alltoall": a2a,
         "grouped": grouped,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -138,6 +138,29 @@ vcclResult_t vcclAllGather(const void* sendbuff, void* recvbuff, size_t sendcoun
 vcclResult_t vcclReduceScatter(const void* sendbuff, void* recvbuff, size_t recvcount, vcclDataType_t datatype,
                                vcclRedOp_t op, vcclComm_t comm, void* stream);
 
+/* Section II-A, "Point-to-Point Communication": vcclSend moves `count`
+ * elements of sendbuff from the calling rank to rank `peer`; vcclRecv receives
+ * them into recvbuff (count elements) on `peer`'s partner.  The k-th Send from
+ * rank a to rank b pairs with the k-th Recv that b posts from a; count and
+ * datatype must agree (vcclInvalidUsage otherwise, returned to the call that
+ * completes the pair).  A pair is issued as soon as both sides are posted:
+ * outside a group at once, inside a group at GroupEnd together with the
+ * group's other calls, so that Send/Recv pairs between every two ranks give
+ * all-to-all, scatter or gather patterns in one launch.  A transfer is split
+ * over channels (one per MiB, Section II-C) and its bytes go straight from
+ * sendbuff into recvbuff with no intermediate FIFO, as in P2P_DIRECT
+ * (Section IV-A); every workgroup of a channel's lane copies a share.  The
+ * launch itself orders the two buffers against all other work, so no head /
+ * tail synchronisation is needed inside it.  peer may be the caller itself
+ * (a local copy).  Buffers are device memory aligned to the
+ * element size, caller-owned, not overlapping; peer outside [0, nranks) or a
+ * null buffer with count > 0 is vcclInvalidArgument.  A group that ends with
+ * a Send or Recv still unpaired returns vcclInvalidUsage and issues nothing. */
+vcclResult_t vcclSend(const void* sendbuff, size_t count, vcclDataType_t datatype, int peer, vcclComm_t comm,
+                      void* stream);
+vcclResult_t vcclRecv(void* recvbuff, size_t count, vcclDataType_t datatype, int peer, vcclComm_t comm,
+                      void* stream);
+
 /* Section II-A, "Group Calls": calls between GroupStart and GroupEnd are
  * deferred and executed together as part of one launch.  Groups nest; the
  * outermost GroupEnd plans every collective matched inside the group (per

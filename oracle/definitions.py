@@ -6,6 +6,8 @@ meaning is the standard one) -- brute force, no schedule.
 * AllGather:     out_r[q*n + i] = x_q[i]
 * Broadcast:     out_r = x_root
 * Reduce:        out_root = (+)_q x_q
+* Send/Recv:     recv_b = send_a (a copy); all-to-all through grouped
+                 Send/Recv: out_b[a*n + i] = x_a[b*n + i]
 
 For int32 sum (mod 2^32) and for max these are exact at every size, because
 those operators are associative and commutative: they pin the schedules
@@ -69,6 +71,21 @@ def broadcast(xs, root):
 def reduce(xs, root, op, dtype):
     v = _reduce_all(xs, op, dtype)
     return [v if r == root else None for r in range(len(xs))]
+
+
+def sendrecv(x):
+    """Point-to-point transfer (Section II-A, Send/Recv): the receiver's
+    buffer ends up holding the sender's elements, bit for bit."""
+    return np.array(x, copy=True)
+
+
+def alltoall(xs):
+    """Send/Recv between every ordered pair of ranks in one group (Section
+    II-A, group calls): rank a sends block b of its buffer (n elements) to
+    rank b, which stores it as block a.  out_b[a*n + i] = x_a[b*n + i]."""
+    R = len(xs)
+    n = len(xs[0]) // R
+    return [np.concatenate([np.asarray(xs[a])[b * n:(b + 1) * n] for a in range(R)]) for b in range(R)]
 
 
 def fp64_sum(arrs, dtype):

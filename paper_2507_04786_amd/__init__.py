@@ -96,6 +96,8 @@ def _load():
         "vcclReduce": (I, [VP, VP, SZ, I, I, I, P, VP]),
         "vcclAllGather": (I, [VP, VP, SZ, I, P, VP]),
         "vcclReduceScatter": (I, [VP, VP, SZ, I, I, P, VP]),
+        "vcclSend": (I, [VP, SZ, I, I, P, VP]),
+        "vcclRecv": (I, [VP, SZ, I, I, P, VP]),
         "vcclGroupStart": (I, []),
         "vcclGroupEnd": (I, []),
         "vcclCommSetTuning": (I, [P, C.POINTER(vcclTuning_t)]),
@@ -123,7 +125,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy vcclCommAbort "
             "vcclCommGetAsyncError vcclCommCount vcclCommUserRank vcclAllReduce vcclBroadcast vcclReduce "
-            "vcclAllGather vcclReduceScatter vcclGroupStart vcclGroupEnd vcclCommSetTuning vcclCommGetLastPlan "
+            "vcclAllGather vcclReduceScatter vcclSend vcclRecv vcclGroupStart vcclGroupEnd vcclCommSetTuning "
+            "vcclCommGetLastPlan "
             "vcclCommGetLastTimestamps vcclCommSetTimeout vcclCommDebugSetDeadRanks vcclCommDebugReadFifo "
             "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
             "vcclServeDestroy vcclServeReplay vcclServeDebugState").split()
@@ -220,6 +223,14 @@ def vcclAllGather(send, recv, sendcount, datatype, comm, stream=None):
 def vcclReduceScatter(send, recv, recvcount, datatype, op, comm, stream=None):
     _check(_lib.vcclReduceScatter(_ptr(send), _ptr(recv), int(recvcount), int(datatype), int(op), comm,
                                   _stream(stream)), "vcclReduceScatter")
+
+
+def vcclSend(send, count, datatype, peer, comm, stream=None):
+    _check(_lib.vcclSend(_ptr(send), int(count), int(datatype), int(peer), comm, _stream(stream)), "vcclSend")
+
+
+def vcclRecv(recv, count, datatype, peer, comm, stream=None):
+    _check(_lib.vcclRecv(_ptr(recv), int(count), int(datatype), int(peer), comm, _stream(stream)), "vcclRecv")
 
 
 def vcclGroupStart():

@@ -671,7 +671,7 @@ __device__ __forceinline__ uint64_t connId(const Ctx& c, int receiver, int kind)
 __device__ __forceinline__ char* fifoOf(const Ctx& c, int proto, int receiver, int kind, uint64_t fifoBytes) {
   const uint64_t lr = (uint64_t)c.lane * c.nranks + receiver;
   if (kind == 0) return c.comm->fifo[proto] + lr * fifoBytes;
-  return c.comm->treeFifo[proto] + (lr * (NCONN - 1) + (kind - 1)) * fifoBytes;
+  return c.comm->treeFifo[proto] + (lr * NTREE_CONN + (kind - 1)) * fifoBytes;
 }
 
 // Thread 0 reads the step counters (a receiver's own head, a sender's own
@@ -950,11 +950,36 @@ __device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
   }
 }
 
+// Point-to-point transfer (Section II-A Send/Recv) in the spirit of
+// P2P_DIRECT (Section IV-A): the bytes go straight from the sender's buffer
+// into the receiver's, with no intermediate FIFO.  Both buffers belong to the
+// same launch, whose start and end order them against every other operation,
+// so no workgroup has to wait for another: every workgroup of the lane copies
+// a 1/R share of the item's range, in slot-sized pieces.  Units are bytes.
+template <int SC>
+__device__ void p2pTransfer(const Ctx& c, const WorkItem& w, const CollArgs& args) {
+  const uint64_t n = w.chCount, R = (uint64_t)c.nranks;
+  const uint64_t per = (n + R - 1) / R;
+  const uint64_t share = (per + 15) / 16 * 16;
+  const uint64_t b0 = umin(n, (uint64_t)c.rank * share), b1 = umin(n, ((uint64_t)c.rank + 1) * share);
+  const char* src = args.send[w.root] + w.chOffset;
+  char* dst = args.recv[w.peer] + w.chOffset;
+  for (uint64_t a0 = b0; a0 < b1; a0 += w.chunk) {
+    PtrList in, out;
+    in.add(src + a0);
+    out.add(dst + a0);
+    reduceCopyN<DT_U8, OP_COPY, SC>(c, in, out, umin(w.chunk, b1 - a0));
+  }
+}
+
 template <int PROTO, int SC, int DT, int OP>
 __device__ __noinline__ void runItem(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   if constexpr (OP == OP_COPY) {
     if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, SC, DT, OP>(c, w, args, sSteps);
     else if (w.coll == COLL_BROADCAST) ringBroadcast<PROTO, SC, DT, OP>(c, w, args, sSteps);
+    else if constexpr (PROTO == PROTO_SIMPLE) {
+      if (w.coll == COLL_SENDRECV) p2pTransfer<SC>(c, w, args);
+    }
   } else {
     if (w.coll == COLL_ALLREDUCE) {
       if (w.algo == ALGO_TREE) treeAllReduce<PROTO, SC, DT, OP>(c, w, args, sSteps);

@@ -88,6 +88,21 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
       if (r != vcclSuccess) return r;
     }
   }
+  // Point-to-point transfers of a group share the lanes: channels in
+  // proportion to each transfer's bytes, about two items per lane in all
+  // (their results do not depend on the split; an explicit channel count
+  // is kept)
+  if (colls.size() > 1 && c->apiTune.nchannels <= 0 && c->envTune.nchannels <= 0) {
+    double p2pBytes = 0;
+    for (const auto& x : colls)
+      if (x.coll == COLL_SENDRECV) p2pBytes += (double)x.count * dtypeBytes(x.dtype);
+    const int L = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
+    for (size_t g = 0; g < colls.size() && p2pBytes > 0; ++g) {
+      if (colls[g].coll != COLL_SENDRECV) continue;
+      const double share = (double)colls[g].count * dtypeBytes(colls[g].dtype) / p2pBytes;
+      plans[g].nchannels = std::max(1, std::min(plans[g].nchannels, (int)std::ceil(share * 2 * L)));
+    }
+  }
   StreamSet ss;
   for (const auto& x : colls)
     for (int r = 0; r < R; ++r) ss.add(x.streams[r]);
@@ -336,6 +351,63 @@ static vcclResult_t enqueueCall(vcclComm_t comm, const Call& call) {
   return launchColls(c, one, false);
 }
 
+// Send / Recv (Section II-A): the k-th send from rank a to rank b pairs with
+// the k-th receive posted by b from a.  A pair is issued once both sides are
+// posted: inside a group at GroupEnd, together with the group's other work,
+// outside a group at once.
+static vcclResult_t enqueueP2p(vcclComm_t comm, bool isSend, void* buf, size_t count, int dtype, int peer,
+                               hipStream_t stream) {
+  if (!validHandle(comm)) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  if (c->aborted) return vcclRemoteError;
+  const int R = c->nranks;
+  if (dtype < vcclInt32 || dtype > vcclBfloat16) return vcclInvalidArgument;
+  if (peer < 0 || peer >= R) return vcclInvalidArgument;
+  if (count > 0 && !buf) return vcclInvalidArgument;
+  if ((uintptr_t)buf % dtypeBytes(dtype)) return vcclInvalidArgument;
+  if (count > ((size_t)1 << 40)) return vcclInvalidArgument;
+  const int me = comm->rank;
+  const int sender = isSend ? me : peer, receiver = isSend ? peer : me;
+  const size_t key = (size_t)sender * R + receiver;
+  (isSend ? c->p2pSends : c->p2pRecvs)[key].push_back(P2pOp{buf, count, dtype, stream});
+  if (tlsGroup.depth > 0 &&
+      std::find(tlsGroup.touched.begin(), tlsGroup.touched.end(), c) == tlsGroup.touched.end())
+    tlsGroup.touched.push_back(c);
+  auto& sq = c->p2pSends[key];
+  auto& rq = c->p2pRecvs[key];
+  if (sq.empty() || rq.empty()) return vcclSuccess;  // wait for the partner
+  const P2pOp snd = sq.front(), rcv = rq.front();
+  sq.pop_front();
+  rq.pop_front();
+  if (snd.count != rcv.count || snd.dtype != rcv.dtype) return vcclInvalidUsage;
+  Coll coll{};
+  coll.coll = COLL_SENDRECV;
+  coll.dtype = snd.dtype;
+  coll.op = vcclSum;
+  coll.root = sender;
+  coll.peer = receiver;
+  coll.count = snd.count;
+  coll.args.send[sender] = (const char*)snd.buf;
+  coll.args.recv[receiver] = (char*)rcv.buf;
+  for (int r = 0; r < R; ++r) coll.streams[r] = snd.stream;
+  coll.streams[receiver] = rcv.stream;
+  if (tlsGroup.depth > 0) {
+    tlsGroup.colls.push_back({c, coll});
+    return vcclSuccess;
+  }
+  std::vector<Coll> one{coll};
+  return launchColls(c, one, false);
+}
+
+vcclResult_t vcclSend(const void* sendbuff, size_t count, vcclDataType_t datatype, int peer, vcclComm_t comm,
+                      void* stream) {
+  return enqueueP2p(comm, true, const_cast<void*>(sendbuff), count, (int)datatype, peer, (hipStream_t)stream);
+}
+
+vcclResult_t vcclRecv(void* recvbuff, size_t count, vcclDataType_t datatype, int peer, vcclComm_t comm, void* stream) {
+  return enqueueP2p(comm, false, recvbuff, count, (int)datatype, peer, (hipStream_t)stream);
+}
+
 vcclResult_t vcclAllReduce(const void* sendbuff, void* recvbuff, size_t count, vcclDataType_t datatype,
                            vcclRedOp_t op, vcclComm_t comm, void* stream) {
   Call x{COLL_ALLREDUCE, (int)datatype, (int)op, 0, count, sendbuff, recvbuff, (hipStream_t)stream};
@@ -383,8 +455,15 @@ vcclResult_t vcclGroupEnd(void) {
     bool incomplete = false;
     for (auto& q : c->pending)
       if (!q.empty()) incomplete = true;
+    for (auto* qs : {&c->p2pSends, &c->p2pRecvs})
+      for (auto& q : *qs)
+        if (!q.empty()) incomplete = true;
     if (incomplete) {
+      // a call whose partners never came (a collective not called by every
+      // rank, a send without its receive): nothing of this set is launched
       for (auto& q : c->pending) q.clear();
+      for (auto* qs : {&c->p2pSends, &c->p2pRecvs})
+        for (auto& q : *qs) q.clear();
       result = vcclInvalidUsage;
       continue;
     }

@@ -102,6 +102,8 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   if (c->maxLanes < 1) c->maxLanes = 1;
   if (c->maxLanes > MAX_LANES) c->maxLanes = MAX_LANES;
   c->pending.resize(nranks);
+  c->p2pSends.resize((size_t)nranks * nranks);
+  c->p2pRecvs.resize((size_t)nranks * nranks);
   auto fail = [&](hipError_t e, const char* what) {
     logError(what, e, __FILE__, __LINE__);
     cliqueFree(c);
@@ -238,7 +240,7 @@ vcclResult_t cliqueEnsureTreeFifos(Clique* c) {
   if (c->treeFifo[0]) return vcclSuccess;
   VCCL_HIPCHECK(hipDeviceSynchronize());
   for (int p = 0; p < 3; ++p) {
-    const uint64_t bytes = (uint64_t)c->maxLanes * c->nranks * (NCONN - 1) * NSLOTS * c->host.slotBytes[p];
+    const uint64_t bytes = (uint64_t)c->maxLanes * c->nranks * NTREE_CONN * NSLOTS * c->host.slotBytes[p];
     VCCL_HIPCHECK(hipMalloc((void**)&c->treeFifo[p], bytes));
     if (p != PROTO_SIMPLE) VCCL_HIPCHECK(hipMemset(c->treeFifo[p], 0, bytes));
     c->host.treeFifo[p] = c->treeFifo[p];

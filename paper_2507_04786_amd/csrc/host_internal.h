@@ -35,13 +35,23 @@ struct Call {
   hipStream_t stream;
 };
 
-// A collective whose R per-rank calls have all arrived.
+// A posted Send or Recv waiting for its partner.
+struct P2pOp {
+  void* buf;
+  size_t count;
+  int dtype;
+  hipStream_t stream;
+};
+
+// A collective whose R per-rank calls have all arrived, or a matched
+// point-to-point transfer (coll COLL_SENDRECV: root = sender, peer = receiver).
 struct Coll {
   uint8_t coll;
   int dtype, op, root;
   size_t count;
   CollArgs args;
   hipStream_t streams[MAX_RANKS];
+  int peer = 0;
 };
 
 struct Plan {
@@ -83,6 +93,9 @@ struct Clique {
   std::vector<hipEvent_t> joinEvents;
   // matching
   std::vector<std::deque<Call>> pending;  // per rank
+  // point-to-point: [sender * nranks + receiver] posted sends and receives,
+  // matched in order per ordered pair
+  std::vector<std::deque<P2pOp>> p2pSends, p2pRecvs;
   // tuning
   Tuning envTune, apiTune;
   bool cooperative = true;

@@ -15,6 +15,7 @@ size_t dtypeBytes(int dtype) { return dtype == vcclBfloat16 ? 2 : 4; }
 // Message size in the nccl-tests convention: the larger per-rank buffer.
 uint64_t collSizeBytes(uint8_t coll, size_t count, int dtype, int nranks) {
   const uint64_t b = (uint64_t)count * dtypeBytes(dtype);
+  if (coll == COLL_SENDRECV) return b;
   if (coll == COLL_ALLGATHER || coll == COLL_REDUCESCATTER) return b * (uint64_t)nranks;
   return b;
 }
@@ -22,12 +23,15 @@ uint64_t collSizeBytes(uint8_t coll, size_t count, int dtype, int nranks) {
 static uint64_t ceilDiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 static uint64_t roundUp(uint64_t a, uint64_t b) { return ceilDiv(a, b) * b; }
 
-static uint64_t unitBytesOf(uint8_t coll, int dtype) {
-  return (coll == COLL_ALLGATHER || coll == COLL_BROADCAST) ? 1 : dtypeBytes(dtype);
+// Copies (AllGather, Broadcast, point-to-point) are partitioned in bytes.
+static bool copyOnly(uint8_t coll) {
+  return coll == COLL_ALLGATHER || coll == COLL_BROADCAST || coll == COLL_SENDRECV;
 }
 
+static uint64_t unitBytesOf(uint8_t coll, int dtype) { return copyOnly(coll) ? 1 : dtypeBytes(dtype); }
+
 static uint64_t unitsOf(uint8_t coll, size_t count, int dtype) {
-  return (coll == COLL_ALLGATHER || coll == COLL_BROADCAST) ? (uint64_t)count * dtypeBytes(dtype) : (uint64_t)count;
+  return copyOnly(coll) ? (uint64_t)count * dtypeBytes(dtype) : (uint64_t)count;
 }
 
 // Largest chunk one slot can carry per protocol (slot payload).
@@ -74,7 +78,38 @@ void channelRange(uint64_t n, int nchannels, uint64_t align, int ch, uint64_t* s
   *count = e - s;
 }
 
+// Point-to-point transfer (Section II-A Send/Recv; Section II-C: grouped
+// transfers spread over channels; Section IV-A: P2P_DIRECT): a direct copy
+// into the receiver's buffer, a channel per 1 MiB up to the lane cap, every
+// workgroup of a lane copying 1/R of each channel, slot-sized pieces.  Only
+// the channel count, threads and chunk follow an explicit tuning.
+static vcclResult_t planP2p(Clique* c, const Coll& coll, Plan* plan) {
+  const int R = c->nranks;
+  const uint64_t S = (uint64_t)coll.count * dtypeBytes(coll.dtype);
+  auto pickPos = [&](long api, long env, long dflt) { return api > 0 ? api : (env > 0 ? env : dflt); };
+  const int laneCap = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
+  const long dfltC = (long)std::min<uint64_t>((uint64_t)laneCap, std::max<uint64_t>(1, ceilDiv(S, 1u << 20)));
+  int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
+  nch = std::max(1, std::min(nch, c->maxLanes));
+  int nthreads = (int)pickPos(c->apiTune.nthreads, c->envTune.nthreads, 256);
+  nthreads = std::max(64, std::min(1024, nthreads / 64 * 64));
+  const int occ = cliqueOccupancy(c, nthreads);
+  if (occ <= 0) return vcclInternalError;
+  while (nch > 1 && 8 * R * (int)ceilDiv(nch, 8) > c->numCUs * occ) --nch;
+  uint64_t chunk = c->apiTune.chunkBytes ? c->apiTune.chunkBytes
+                                         : (c->envTune.chunkBytes ? c->envTune.chunkBytes : maxChunkBytes(c, PROTO_SIMPLE));
+  chunk = std::max<uint64_t>(16, std::min(chunk, maxChunkBytes(c, PROTO_SIMPLE)) / 16 * 16);
+  plan->algo = ALGO_RING;
+  plan->proto = PROTO_SIMPLE;
+  plan->nchannels = nch;
+  plan->nthreads = nthreads;
+  plan->direct = 1;
+  plan->chunkBytes = chunk;
+  return vcclSuccess;
+}
+
 vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
+  if (coll.coll == COLL_SENDRECV) return planP2p(c, coll, plan);
   const int R = c->nranks;
   const uint64_t S = collSizeBytes(coll.coll, coll.count, coll.dtype, R);
   auto pick = [&](int api, int env, int dflt) { return api >= 0 ? api : (env >= 0 ? env : dflt); };
@@ -157,16 +192,17 @@ void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t arg
     w.coll = coll.coll;
     w.algo = (uint8_t)plan.algo;
     w.proto = (uint8_t)plan.proto;
-    const bool copyOnly = coll.coll == COLL_ALLGATHER || coll.coll == COLL_BROADCAST;
-    w.dtype = copyOnly ? DT_U8 : (uint8_t)(coll.dtype == vcclInt32 ? DT_I32 : coll.dtype == vcclFloat32 ? DT_F32 : DT_BF16);
-    w.op = copyOnly ? OP_COPY : (uint8_t)(coll.op == vcclMax ? OP_MAX : OP_SUM);
+    const bool copy = copyOnly(coll.coll);
+    w.dtype = copy ? DT_U8 : (uint8_t)(coll.dtype == vcclInt32 ? DT_I32 : coll.dtype == vcclFloat32 ? DT_F32 : DT_BF16);
+    w.op = copy ? OP_COPY : (uint8_t)(coll.op == vcclMax ? OP_MAX : OP_SUM);
     w.direct = (uint8_t)plan.direct;
     w.tree = (uint8_t)(ch % 2);
+    w.peer = (uint8_t)coll.peer;
     w.root = coll.root;
     w.argsIndex = argsIndex;
     w.doneIndex = doneIndex;
     w.unitBytes = (uint32_t)ub;
-    w.elemBytes = (uint32_t)(copyOnly ? 1 : dtypeBytes(coll.dtype));
+    w.elemBytes = (uint32_t)(copy ? 1 : dtypeBytes(coll.dtype));
     w.count = n;
     channelRange(n, plan.nchannels, align, ch, &w.chOffset, &w.chCount);
     w.chunk = plan.chunkBytes / ub;
@@ -189,6 +225,10 @@ double estimateCost(const Clique* c, const WorkItem& w) {
   } else if (w.coll == COLL_ALLGATHER || w.coll == COLL_REDUCESCATTER) {
     steps = (double)R * std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes));
     traffic = (R + 1.0 + 2.0 * fifo * (R - 1)) * bytes;
+  } else if (w.coll == COLL_SENDRECV) {
+    // a read and a direct write per byte, shared by the lane's workgroups
+    steps = std::ceil(bytes / std::max<double>(1.0, (double)R * w.chunk * w.unitBytes));
+    traffic = 2.0 * bytes;
   } else {
     steps = std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes)) + R;
     traffic = (R + 1.0 + 2.0 * fifo * (R - 1)) * bytes;

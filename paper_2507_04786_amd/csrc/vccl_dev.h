@@ -22,14 +22,16 @@
 
 namespace vccl {
 
-enum : uint8_t { COLL_ALLREDUCE = 0, COLL_BROADCAST = 1, COLL_REDUCE = 2, COLL_ALLGATHER = 3, COLL_REDUCESCATTER = 4 };
+enum : uint8_t { COLL_ALLREDUCE = 0, COLL_BROADCAST = 1, COLL_REDUCE = 2, COLL_ALLGATHER = 3, COLL_REDUCESCATTER = 4,
+                  COLL_SENDRECV = 5 };
 enum : uint8_t { ALGO_RING = 0, ALGO_TREE = 1 };
 enum : uint8_t { PROTO_SIMPLE = 0, PROTO_LL = 1, PROTO_LL128 = 2 };
 enum : uint8_t { DT_I32 = 0, DT_F32 = 1, DT_BF16 = 2, DT_U8 = 3 };
 enum : uint8_t { OP_SUM = 0, OP_MAX = 1, OP_COPY = 2 };
 
 constexpr int NSLOTS = 8;
-constexpr int NCONN = 7;
+constexpr int NTREE_CONN = 6;   // tree connection kinds 1..6
+constexpr int NCONN = 1 + NTREE_CONN;
 constexpr int MAX_RANKS = 16;
 constexpr int MAX_LANES = 64;
 constexpr int MAX_INLINE = 32;
@@ -71,8 +73,8 @@ struct DevComm {
 // One channel-slice of one collective, run by one lane (one workgroup per rank).
 struct WorkItem {
   uint8_t coll, algo, proto, dtype;
-  uint8_t op, direct, tree, pad;
-  int32_t root;
+  uint8_t op, direct, tree, peer;  // peer: receiving rank of a point-to-point transfer
+  int32_t root;                    // root, or the sending rank of a point-to-point transfer
   uint32_t argsIndex;
   uint32_t doneIndex;        // completion record index, 0xFFFFFFFF = none
   uint32_t unitBytes;        // 1 (AllGather, Broadcast) or the element size

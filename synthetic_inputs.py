@@ -34,6 +34,7 @@ WL_RING_AR_SWEEP = 2      # ring AllReduce, 8 ranks, fp32 N(0,1), 8 B .. 256 MiB
 WL_TREE_AND_CHAINS = 3    # tree AllReduce + ring Bcast/Reduce/AG/RS, 16 ranks
 WL_GROUPED = 4            # 64 grouped collectives, 8 ranks
 WL_SERVING = 5            # Poisson request stream, 8 ranks
+WL_P2P = 6                # Send/Recv pairs and grouped all-to-all
 
 
 def rng_for(workload_id: int, rank: int, extra: int | None = None) -> np.random.Generator:
