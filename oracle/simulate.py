@@ -119,7 +119,7 @@ def _run(programs: dict, slots: int, op_name: str, dtype: str, trace: list | Non
                 for k in op.send_to:
                     fifo(k).append((op.tag, value.copy()))
                 if trace is not None:
-                    ent = dict(rank=r, prim=op.prim, tag=op.tag)
+                    ent = dict(rank=r, prim=op.prim, tag=op.tag, sent_bytes=int(value.nbytes) * len(op.send_to))
                     ent.update(op.info)
                     trace.append(ent)
                 pcs[r] += 1

@@ -228,6 +228,34 @@ def test_transfer_counts_per_loop(R):
             assert sends == calls - 1 and recvs == calls - 1
 
 
+@pytest.mark.parametrize("R", [2, 4, 8, 16])
+def test_link_bytes_give_the_bus_bandwidth_factors(R):
+    """Bytes each rank puts on its outgoing link, over the message size S
+    (nccl-tests convention: busBW = algBW x factor): ring AllReduce
+    2(R-1)/R, ReduceScatter and AllGather (R-1)/R, Broadcast and Reduce 1
+    for every rank but the last of the chain (which sends nothing)."""
+    n = 64 * R  # elements per rank; divisible by R and the chunk
+    xs = si.rank_inputs(9, R, "float32", n, extra=R)
+    S = n * 4
+    for coll, factor in (("allreduce", 2 * (R - 1) / R), ("reducescatter", (R - 1) / R),
+                         ("allgather", (R - 1) / R), ("broadcast", 1.0), ("reduce", 1.0)):
+        data = list(xs)
+        if coll == "allgather":
+            data = [x[: n // R] for x in xs]  # S = the gathered (larger) buffer
+        tr = []
+        sim.run(coll, data, dtype="float32", nchannels=2, chunk_bytes=32, root=1, trace=tr)
+        sent = {}
+        for e in tr:
+            sent[e["rank"]] = sent.get(e["rank"], 0) + e["sent_bytes"]
+        for r in range(R):
+            if coll == "broadcast" and r == 0:    # root 1: the last of the chain is rank 0
+                assert sent.get(r, 0) == 0
+            elif coll == "reduce" and r == 1:     # the chain ends at the root
+                assert sent.get(r, 0) == 0
+            else:
+                assert sent[r] == factor * S, (coll, R, r, sent[r], factor * S)
+
+
 # ---------------------------------------------------------------- brute force
 
 CASES = [(2, 1, 16), (3, 2, 32), (4, 1, 64), (5, 3, 48), (8, 4, 16), (16, 2, 128)]
