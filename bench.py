@@ -54,18 +54,27 @@ def alg_bytes_per_launch(plan: dict, nranks: int, size: int) -> float:
     return (2 * R + 4 * f * (R - 1)) * size
 
 
+def kernel_source_digest() -> str:
+    """Digest of the kernel's sources (device code and the structures it
+    shares with the host): a recorded counter reading applies while it is
+    unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("device.hip", "vccl_dev.h"):
+        with open(os.path.join(ROOT, "paper_2507_04786_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def load_traffic(kernel_key: str):
     """HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE,
-    from profiles/<key>.traffic.json when it was taken on the current build."""
+    from profiles/<key>.traffic.json when it was taken on the current kernel."""
     path = os.path.join(ROOT, "profiles", kernel_key + ".traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        lib = os.path.join(ROOT, "paper_2507_04786_amd", "lib", "libvccl.so")
-        import hashlib
-        digest = hashlib.sha256(open(lib, "rb").read()).hexdigest()[:16]
-        if rec.get("lib_sha256_16") != digest:
+        if rec.get("kernel_src_sha256_16") != kernel_source_digest():
             return None
         return float(rec["bytes_per_launch"])
     except Exception:
