@@ -193,7 +193,9 @@ typedef struct {
   int algo, proto, nchannels, nthreads, direct, nlanes, nitems, ncolls;
   size_t chunkBytes;
   int grid;           /* workgroups launched */
-  int scope;          /* 0: peers anywhere on the device, 1: each channel on one XCD */
+  int scope;          /* store policy chosen for the (first) collective: 0 device-coherent
+                         stores, 1 plain stores into the XCD's L2 (each channel's
+                         workgroups share an XCD; loads are device-coherent in both) */
 } vcclPlanInfo_t;
 vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info);
 
@@ -223,8 +225,11 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
  * runs `pairs` writer/reader workgroup pairs that exchange `lines` lines per
  * round for `rounds` rounds, every payload word derived from (flag, index);
  * *torn receives the number of lines whose flag was current but whose
- * payload was not.  Synchronises the device. */
-vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, uint64_t* torn, uint64_t* checked);
+ * payload was not.  scope selects the store policy of the lines: 0 device
+ * scope (sc1 stores; with pairs = 4 writer and reader sit on different XCDs),
+ * 1 XCD scope (plain stores into the shared L2; pairs must be a multiple of 8
+ * so that each pair shares an XCD).  Synchronises the device. */
+vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uint64_t* torn, uint64_t* checked);
 
 /* XCC (accelerator die) id of each of `n` workgroups of a plain launch,
  * written to the host array ids[n].  Synchronises the device. */

@@ -106,7 +106,7 @@ def _load():
         "vcclCommSetTimeout": (I, [P, U64]),
         "vcclCommDebugSetDeadRanks": (I, [P, C.c_uint32]),
         "vcclCommDebugReadFifo": (I, [P, I, I, I, SZ, VP, SZ]),
-        "vcclProbeLL128Tear": (I, [I, I, I, C.POINTER(U64), C.POINTER(U64)]),
+        "vcclProbeLL128Tear": (I, [I, I, I, I, C.POINTER(U64), C.POINTER(U64)]),
         "vcclProbeXccIds": (I, [I, C.POINTER(I)]),
         "vcclServeCreate": (I, [C.POINTER(P), SZ, I, C.POINTER(P)]),
         "vcclServeSubmit": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64)]),
@@ -274,9 +274,10 @@ def vcclCommDebugReadFifo(comm, channel, rank, proto, offset, nbytes) -> bytes:
     return bytes(buf)
 
 
-def vcclProbeLL128Tear(pairs: int, lines: int, rounds: int):
+def vcclProbeLL128Tear(pairs: int, lines: int, rounds: int, scope: int = 0):
+    """scope 0: device-scope (sc1) stores; 1: XCD-scope plain stores (pairs a multiple of 8)."""
     torn, checked = C.c_uint64(), C.c_uint64()
-    res = _lib.vcclProbeLL128Tear(int(pairs), int(lines), int(rounds), C.byref(torn), C.byref(checked))
+    res = _lib.vcclProbeLL128Tear(int(pairs), int(lines), int(rounds), int(scope), C.byref(torn), C.byref(checked))
     if res not in (vcclSuccess, vcclRemoteError):
         raise VcclError(res, "vcclProbeLL128Tear")
     return torn.value, checked.value, res

@@ -58,47 +58,58 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t makeRsrc(const void* base, uin
 }
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
-// Scope of the bulk data traffic of the Simple protocol (DevComm::scope).
-//  SCOPE_DEVICE: peers may sit on any XCD: chunks are stored and loaded with
-//    device-scope coherent accesses (sc1, as relaxed device-scope atomics do),
-//    so draining the stores before the tail store is the whole release and no
-//    cache-wide write-back or invalidate is needed.
+// Memory policy of everything that passes between the workgroups of a lane:
+// chunks and direct writes (Simple), counters, LL units and LL128 lines
+// (DevComm::scope).  Loads are always device-scope coherent (sc1): they skip
+// the CU cache and read the XCD's L2, or memory when the line is not there.
+//  SCOPE_DEVICE: stores are device-scope coherent too (sc1), so they reach
+//    memory and a reader on any XCD sees them.
 //  SCOPE_XCD: every workgroup of a lane runs on the same XCD (roles are
-//    claimed per XCD at kernel start), so that XCD's L2 is the point of
-//    coherence for the chunk: the producer stores through the write-through CU
-//    cache into L2 and drains; the consumer, once it has seen the tail,
-//    invalidates its CU cache (buffer_inv sc0 -- the acquire of the workgroup
-//    scope in threadgroup-split mode, where waves share only L2) and loads
-//    plainly, hitting L2 while the chunk is still there.
-// Flags, counters and the LL / LL128 lines always use device scope.
-template <int SC> struct Aux { static constexpr int value = 16; };
+//    claimed per XCD at kernel start), so the XCD's L2 is the meeting point:
+//    stores are plain (through the write-through CU cache into L2) and the
+//    reader's sc1 loads hit the line there.  A flag round trip between two
+//    workgroups of one XCD takes about half the time of the device-scope
+//    pair (measured on the device with a ping-pong of flags).  Plain stores
+//    are never read by another XCD within the launch; the end of the launch
+//    writes the L2 back.
+// In both, draining a wave's stores (vmcnt 0) before the counter or flag that
+// announces them is the whole release, and the sc1 load of that counter or
+// flag, followed by sc1 loads of the data, is the whole acquire.
+constexpr int LOAD_AUX = 16;  // sc1
+template <int SC> struct StoreAux { static constexpr int value = SC == SCOPE_XCD ? 0 : 16; };
+
+__device__ __forceinline__ void stPlain64(uint64_t* p, uint64_t v) {
+  __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)v, (uint32_t)(v >> 32)}, makeRsrc(p, 8), 0, 0, 0);
+}
 
 template <int SC>
 __device__ __forceinline__ uint64_t ldCtr(const uint64_t* p) { return ldAgent(p); }
 template <int SC>
-__device__ __forceinline__ void stCtr(uint64_t* p, uint64_t v) { stAgent(p, v); }
-// After a tail was observed, before the chunk it announces is read.
-template <int SC>
-__device__ __forceinline__ void acquireData() {
-  if constexpr (SC == SCOPE_XCD) asm volatile("buffer_inv sc0" ::: "memory");
+__device__ __forceinline__ void stCtr(uint64_t* p, uint64_t v) {
+  if constexpr (SC == SCOPE_XCD) stPlain64(p, v);
+  else stAgent(p, v);
 }
+// After a tail was observed, before the chunk it announces is read: the sc1
+// loads of the chunk need no cache invalidation.
+template <int SC>
+__device__ __forceinline__ void acquireData() {}
 // 8-byte LL unit and 16-byte LL128 line access (one instruction each).
 template <int SC>
 __device__ __forceinline__ uint64_t ldUnit(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, Aux<SC>::value);
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, LOAD_AUX);
   return (uint64_t)v.x | ((uint64_t)v.y << 32);
 }
 template <int SC>
 __device__ __forceinline__ void stUnit(__amdgpu_buffer_rsrc_t r, uint32_t off, uint64_t v) {
-  __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)v, (uint32_t)(v >> 32)}, r, off, 0, Aux<SC>::value);
+  __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)v, (uint32_t)(v >> 32)}, r, off, 0, StoreAux<SC>::value);
 }
 template <int SC>
 __device__ __forceinline__ u32x4 ldLine16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, Aux<SC>::value);
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, LOAD_AUX);
 }
 template <int SC>
 __device__ __forceinline__ void stLine16(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, Aux<SC>::value);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, StoreAux<SC>::value);
 }
 
 // ------------------------------------------------------------------ element operators
@@ -283,7 +294,7 @@ struct PtrList {
 // unroll stride in a scalar offset, and hardware range checks (an access past
 // the stream's end reads zero and writes nothing), so the loop needs no
 // per-vector bounds test.
-template <int DT, int OP, int NIN, int NOUT, int CP>
+template <int DT, int OP, int NIN, int NOUT, int LP, int SP>
 __device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, const PtrList& out, uint32_t nvec) {
   constexpr int U = 4;
   const uint32_t nb = nvec * 16;
@@ -298,57 +309,55 @@ __device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, c
     u32x4 v0[U], v1[U], v2[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v0[u] = __builtin_amdgcn_raw_buffer_load_b128(i0, base, u * stride, CP);
-      if constexpr (NIN > 1) v1[u] = __builtin_amdgcn_raw_buffer_load_b128(i1, base, u * stride, CP);
-      if constexpr (NIN > 2) v2[u] = __builtin_amdgcn_raw_buffer_load_b128(i2, base, u * stride, CP);
+      v0[u] = __builtin_amdgcn_raw_buffer_load_b128(i0, base, u * stride, LP);
+      if constexpr (NIN > 1) v1[u] = __builtin_amdgcn_raw_buffer_load_b128(i1, base, u * stride, LP);
+      if constexpr (NIN > 2) v2[u] = __builtin_amdgcn_raw_buffer_load_b128(i2, base, u * stride, LP);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       u32x4 acc = v0[u];
       if constexpr (NIN > 1) acc = redVec4<DT, OP>(acc, v1[u]);
       if constexpr (NIN > 2) acc = redVec4<DT, OP>(acc, v2[u]);
-      __builtin_amdgcn_raw_buffer_store_b128(acc, o0, base, u * stride, CP);
-      if constexpr (NOUT > 1) __builtin_amdgcn_raw_buffer_store_b128(acc, o1, base, u * stride, CP);
-      if constexpr (NOUT > 2) __builtin_amdgcn_raw_buffer_store_b128(acc, o2, base, u * stride, CP);
+      __builtin_amdgcn_raw_buffer_store_b128(acc, o0, base, u * stride, SP);
+      if constexpr (NOUT > 1) __builtin_amdgcn_raw_buffer_store_b128(acc, o1, base, u * stride, SP);
+      if constexpr (NOUT > 2) __builtin_amdgcn_raw_buffer_store_b128(acc, o2, base, u * stride, SP);
     }
   }
 }
 
 // Same operation through element-wise accesses, 16 bytes (or the tail) per
 // lane: the last nbytes % 16 bytes of a step.
-template <int DT, int OP, int NIN, int NOUT, bool COH>
+template <int DT, int OP, int NIN, int NOUT, bool SCOH>
 __device__ __forceinline__ void reduceCopyPart(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t begin,
                                                uint64_t nbytes) {
   constexpr int E = ElemSize<DT>::value;
   for (uint64_t off = begin + (uint64_t)c.tid * 16; off < nbytes; off += (uint64_t)c.nthreads * 16) {
     const int valid = (int)((nbytes - off) < 16 ? (nbytes - off) : 16);
     uint32_t acc[4], w[4];
-    loadPart<E, 4, COH>(in.p0 + off, valid, acc);
+    loadPart<E, 4, true>(in.p0 + off, valid, acc);
     if constexpr (NIN > 1) {
-      loadPart<E, 4, COH>(in.p1 + off, valid, w);
+      loadPart<E, 4, true>(in.p1 + off, valid, w);
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = redWord<DT, OP>(acc[q], w[q]);
     }
     if constexpr (NIN > 2) {
-      loadPart<E, 4, COH>(in.p2 + off, valid, w);
+      loadPart<E, 4, true>(in.p2 + off, valid, w);
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[q] = redWord<DT, OP>(acc[q], w[q]);
     }
-    storePart<E, 4, COH>((char*)out.p0 + off, valid, acc);
-    if constexpr (NOUT > 1) storePart<E, 4, COH>((char*)out.p1 + off, valid, acc);
-    if constexpr (NOUT > 2) storePart<E, 4, COH>((char*)out.p2 + off, valid, acc);
+    storePart<E, 4, SCOH>((char*)out.p0 + off, valid, acc);
+    if constexpr (NOUT > 1) storePart<E, 4, SCOH>((char*)out.p1 + off, valid, acc);
+    if constexpr (NOUT > 2) storePart<E, 4, SCOH>((char*)out.p2 + off, valid, acc);
   }
 }
 
-// SC: SCOPE_DEVICE -> device-scope coherent accesses on every stream of the
-// step; SCOPE_XCD -> plain accesses (the consumer invalidated its CU cache).
+// Loads of every stream are sc1; stores follow the scope (sc1 for
+// SCOPE_DEVICE, plain for SCOPE_XCD).
 template <int DT, int OP, int NIN, int NOUT, int SC>
 __device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
-  constexpr int CP = SC == SCOPE_DEVICE ? 16 : 0;  // sc1
-  constexpr bool COH = SC == SCOPE_DEVICE;
   const uint32_t nvec = (uint32_t)(nbytes / 16);
-  reduceCopyVec<DT, OP, NIN, NOUT, CP>(c, in, out, nvec);
-  if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT, COH>(c, in, out, (uint64_t)nvec * 16, nbytes);
+  reduceCopyVec<DT, OP, NIN, NOUT, LOAD_AUX, StoreAux<SC>::value>(c, in, out, nvec);
+  if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT, SC == SCOPE_DEVICE>(c, in, out, (uint64_t)nvec * 16, nbytes);
 }
 
 template <int DT, int OP, int SC>
@@ -486,7 +495,8 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     sout[i] = makeRsrc(s[i].fifo + (s[i].step % NSLOTS) * (uint64_t)slotB, slotB);
   }
   // user buffers: full 8-byte pieces through buffer accesses at any element
-  // alignment, the short last piece element by element
+  // alignment, the short last piece element by element; reads are sc1 like
+  // every other read of data another workgroup may have written
   const __amdgpu_buffer_rsrc_t bsrc = makeRsrc(a.src, (uint32_t)a.nbytes);
   const __amdgpu_buffer_rsrc_t bdst = makeRsrc(a.dst, (uint32_t)a.nbytes);
   const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
@@ -498,11 +508,11 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     bool have = false;
     if (a.src) {
       if (valid == 8) {
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)off, 0, 0);
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)off, 0, LOAD_AUX);
         acc[0] = v.x;
         acc[1] = v.y;
       } else {
-        loadPart<E, 2>(a.src + off, valid, acc);
+        loadPart<E, 2, true>(a.src + off, valid, acc);
       }
       have = true;
     }
@@ -582,18 +592,18 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
         // user buffers: full pieces through buffer accesses at any element
         // alignment, a short piece element by element
         if (plen == 16) {
-          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(bsrc, (uint32_t)payOff, 0, 0);
+          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(bsrc, (uint32_t)payOff, 0, LOAD_AUX);
           acc[0] = v.x;
           acc[1] = v.y;
           acc[2] = v.z;
           acc[3] = v.w;
         } else {
-          const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)payOff, 0, 0);
+          const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)payOff, 0, LOAD_AUX);
           acc[0] = v.x;
           acc[1] = v.y;
         }
       } else if (valid > 0) {
-        loadPart<E, 4>(a.src + payOff, valid, acc);
+        loadPart<E, 4, true>(a.src + payOff, valid, acc);
       }
       have = true;
     }
@@ -1008,8 +1018,14 @@ __device__ void dispatchType(const Ctx& c, const WorkItem& w, const CollArgs& ar
 }
 
 __device__ __forceinline__ void dispatchItem(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
-  if (c.comm->scope == SCOPE_XCD && w.proto == PROTO_SIMPLE) {
-    dispatchType<PROTO_SIMPLE, SCOPE_XCD>(c, w, args, sSteps);
+  // XCD scope only where the set runs with the lane map (every lane's
+  // workgroups on one XCD) and the plan chose it for this item
+  if (c.comm->scope == SCOPE_XCD && w.scope == SCOPE_XCD) {
+    switch (w.proto) {
+      case PROTO_SIMPLE: dispatchType<PROTO_SIMPLE, SCOPE_XCD>(c, w, args, sSteps); break;
+      case PROTO_LL: dispatchType<PROTO_LL, SCOPE_XCD>(c, w, args, sSteps); break;
+      default: dispatchType<PROTO_LL128, SCOPE_XCD>(c, w, args, sSteps); break;
+    }
   } else {
     switch (w.proto) {
       case PROTO_SIMPLE: dispatchType<PROTO_SIMPLE, SCOPE_DEVICE>(c, w, args, sSteps); break;
@@ -1236,8 +1252,10 @@ __global__ void xccProbeKernel(int* ids, int n) {
   if (threadIdx.x == 0 && (int)blockIdx.x < n) ids[blockIdx.x] = (int)(x & 0xF);
 }
 
-// LL128 tear probe: workgroup 2p writes, workgroup 2p+1 (or 2p+8: another
-// placement) reads `lines` lines per round.  Payload word q of line i in
+// LL128 tear probe: workgroup w < pairs writes, workgroup pairs + w reads
+// `lines` lines per round (workgroups are dispatched round-robin over the 8
+// XCDs, so with pairs a multiple of 8 each pair shares an XCD, with pairs = 4
+// it does not).  SC picks the store policy of the protocol's lines.  Payload word q of line i in
 // round r is a hash of (r, i, q); a line whose flag is current but whose
 // payload differs is a torn line.  The writer waits for the reader's ack
 // before reusing the buffer.  Every wait is bounded by `maxTicks`.
@@ -1249,6 +1267,7 @@ __device__ __forceinline__ uint32_t tearHash(uint32_t r, uint32_t i, uint32_t q)
   return h;
 }
 
+template <int SC>
 __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* acks, int pairs, int lines, int rounds,
                                                         unsigned long long* counts, uint64_t maxTicks,
                                                         uint32_t* failed) {
@@ -1286,7 +1305,7 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
             v.z = (uint32_t)flag;
             v.w = (uint32_t)(flag >> 32);
           }
-          stLine16<SCOPE_DEVICE>(rs, line * LL128_LINE + 16 * j, v);
+          stLine16<SC>(rs, line * LL128_LINE + 16 * j, v);
         }
       }
     } else {
@@ -1294,7 +1313,7 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
         const int line = L0 + g;
         const bool act = line < lines;
         const uint32_t loff = (uint32_t)line * LL128_LINE + 16u * j;
-        u32x4 v = act ? ldLine16<SCOPE_DEVICE>(rs, loff) : u32x4{0, 0, 0, 0};
+        u32x4 v = act ? ldLine16<SC>(rs, loff) : u32x4{0, 0, 0, 0};
         const uint64_t t0 = nowTicks();
         bool tornSeen = false;
         for (;;) {
@@ -1313,7 +1332,7 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
           const bool done = lineOk && lineData;
           if (__all(done)) break;
           if (__any(nowTicks() - t0 > maxTicks)) { atomicOr(&sFail, 1); break; }
-          if (!done && act) v = ldLine16<SCOPE_DEVICE>(rs, loff);
+          if (!done && act) v = ldLine16<SC>(rs, loff);
         }
         if (act && j == 0) checked++;
         if (*(volatile int*)&sFail) break;
@@ -1360,7 +1379,9 @@ hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream) {
 }
 
 hipError_t vcclLaunchTearProbe(char* bufs, uint64_t* acks, int pairs, int lines, int rounds, unsigned long long* counts,
-                               uint64_t maxTicks, uint32_t* failed, hipStream_t stream) {
+                               uint64_t maxTicks, uint32_t* failed, int scope, hipStream_t stream) {
   void* args[] = {&bufs, &acks, &pairs, &lines, &rounds, &counts, &maxTicks, &failed};
-  return hipLaunchCooperativeKernel((const void*)vccl::tearProbeKernel, dim3(2 * pairs), dim3(256), args, 0, stream);
+  const void* k = scope == vccl::SCOPE_XCD ? (const void*)vccl::tearProbeKernel<vccl::SCOPE_XCD>
+                                           : (const void*)vccl::tearProbeKernel<vccl::SCOPE_DEVICE>;
+  return hipLaunchCooperativeKernel(k, dim3(2 * pairs), dim3(256), args, 0, stream);
 }

@@ -203,7 +203,7 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   info.nitems = (int)nitems;
   info.ncolls = (int)colls.size();
   info.grid = grid;
-  info.scope = (int)c->host.scope;
+  info.scope = plans[0].scope;
   (void)grouped;
   return vcclSuccess;
 }
@@ -568,9 +568,11 @@ vcclResult_t vcclProbeXccIds(int n, int* ids) {
   return vcclSuccess;
 }
 
-vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, uint64_t* torn, uint64_t* checked) {
+vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uint64_t* torn, uint64_t* checked) {
   if (pairs < 1 || pairs > 64 || lines < 1 || lines > 65536 || rounds < 1 || !torn || !checked)
     return vcclInvalidArgument;
+  if (scope != SCOPE_DEVICE && scope != SCOPE_XCD) return vcclInvalidArgument;
+  if (scope == SCOPE_XCD && pairs % 8) return vcclInvalidArgument;  // plain stores: each pair on one XCD
   char* bufs = nullptr;
   uint64_t* acks = nullptr;
   unsigned long long* counts = nullptr;
@@ -588,7 +590,7 @@ vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, uint64_t* torn
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, dev);
   const uint64_t maxTicks = (uint64_t)wallKHz * 1000ull * 5ull;  // 5 s per wait
-  hipError_t e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, nullptr);
+  hipError_t e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, scope, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   unsigned long long h[2] = {0, 0};
   uint32_t hf = 0;

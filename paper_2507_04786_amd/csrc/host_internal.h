@@ -19,7 +19,8 @@ hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream);
 hipError_t vcclLaunchServe(const vccl::ServeDesc& d, int grid, int block, hipStream_t stream);
 hipError_t vcclServeOccupancy(int block, int* blocksPerCU);
 hipError_t vcclLaunchTearProbe(char* bufs, uint64_t* acks, int pairs, int lines, int rounds,
-                               unsigned long long* counts, uint64_t maxTicks, uint32_t* failed, hipStream_t stream);
+                               unsigned long long* counts, uint64_t maxTicks, uint32_t* failed, int scope,
+                               hipStream_t stream);
 
 namespace vccl {
 
@@ -57,6 +58,7 @@ struct Coll {
 struct Plan {
   int algo, proto, nchannels, nthreads, direct;
   uint64_t chunkBytes;
+  int scope = SCOPE_DEVICE;
 };
 
 struct Tuning {
@@ -106,6 +108,7 @@ struct Clique {
   std::vector<vcclComm*> handles;
   int occupancy[17] = {0};    // blocks per CU for nthreads = 64 * index
   bool serving = false;       // a persistent serving kernel owns the lanes
+  uint64_t deviceScopeBytes = 0;  // Simple items of collectives this large use device scope
   uint64_t* claim = nullptr;  // per-XCD role counters (device)
   uint64_t claimBase = 0;     // role claims of all launches so far, per XCD
 };

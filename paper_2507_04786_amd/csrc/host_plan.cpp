@@ -105,6 +105,7 @@ static vcclResult_t planP2p(Clique* c, const Coll& coll, Plan* plan) {
   plan->nthreads = nthreads;
   plan->direct = 1;
   plan->chunkBytes = chunk;
+  plan->scope = (c->host.scope == SCOPE_XCD && S < c->deviceScopeBytes) ? SCOPE_XCD : SCOPE_DEVICE;
   return vcclSuccess;
 }
 
@@ -179,6 +180,9 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   plan->nthreads = nthreads;
   plan->direct = direct;
   plan->chunkBytes = chunk;
+  // store policy: XCD scope (lower latency) unless a large Simple transfer
+  plan->scope = (c->host.scope == SCOPE_XCD && !(proto == PROTO_SIMPLE && S >= c->deviceScopeBytes))
+                    ? SCOPE_XCD : SCOPE_DEVICE;
   return vcclSuccess;
 }
 
@@ -203,6 +207,7 @@ void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t arg
     w.doneIndex = doneIndex;
     w.unitBytes = (uint32_t)ub;
     w.elemBytes = (uint32_t)(copy ? 1 : dtypeBytes(coll.dtype));
+    w.scope = (uint8_t)plan.scope;
     w.count = n;
     channelRange(n, plan.nchannels, align, ch, &w.chOffset, &w.chCount);
     w.chunk = plan.chunkBytes / ub;

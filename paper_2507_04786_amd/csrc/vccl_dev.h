@@ -79,11 +79,15 @@ struct WorkItem {
   uint32_t doneIndex;        // completion record index, 0xFFFFFFFF = none
   uint32_t unitBytes;        // 1 (AllGather, Broadcast) or the element size
   uint32_t elemBytes;
+  uint8_t scope;             // SCOPE_DEVICE or SCOPE_XCD: store policy of this item's traffic
+  uint8_t pad[3];
   uint64_t count;            // units per rank (per block for AllGather / ReduceScatter)
   uint64_t chOffset;         // workOffset of this channel, units
   uint64_t chCount;          // channelCount, units
   uint64_t chunk;            // chunkCount, units
 };
+
+static_assert(sizeof(WorkItem) == 64, "work items are 64 bytes");
 
 struct CollArgs {
   const char* send[MAX_RANKS];

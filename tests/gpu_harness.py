@@ -79,8 +79,9 @@ def untune(vccl, comms):
 
 
 def init_comms(vccl, R, scope="auto"):
-    """Communicator set; scope "xcd" / "device" selects the Simple protocol's
-    chunk traffic scope (VCCL_SCOPE), "auto" the library default."""
+    """Communicator set; scope "xcd" / "device" selects the store policy of
+    the traffic between a lane's workgroups (VCCL_SCOPE), "auto" the library
+    default (XCD scope)."""
     import os
     old = os.environ.get("VCCL_SCOPE")
     if scope in ("device", "xcd"):

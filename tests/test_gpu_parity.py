@@ -311,28 +311,43 @@ def test_large_allreduce_sampled_and_bounded(vccl, comms_for):
 
 
 @pytest.mark.parametrize("proto", PROTOS)
-def test_xcd_scope_path(vccl, comms_for, proto):
-    """Opt-in path: the Simple protocol's chunks travel through the L2 of the
-    XCD every workgroup of the lane was placed on (flags stay device scope)."""
+def test_device_scope_path(vccl, comms_for, proto):
+    """VCCL_SCOPE=device: every store device-coherent (sc1), the path for
+    lanes whose workgroups are not known to share an XCD."""
     for (R, n, C, chunk) in [(4, 70001, 4, 4096), (16, 3001, 3, 512), (8, 65543, 9, 2048)]:
-        comms = comms_for(R, "xcd")
+        comms = comms_for(R, "device")
         for coll, algo in (("allreduce", "ring"), ("allreduce", "tree"), ("reducescatter", "ring"),
                            ("allgather", "ring")):
             xs = _inputs(R, "float32", H.send_len(coll, n, R), extra=5)
             H.tune(vccl, comms, algo, proto, nchannels=C, chunk=chunk)
             try:
                 got = _run(vccl, comms, coll, xs, n, "float32")
-                assert vccl.vcclCommGetLastPlan(comms[0])["scope"] == 1
+                assert vccl.vcclCommGetLastPlan(comms[0])["scope"] == 0
             finally:
                 H.untune(vccl, comms)
             want = sim.run(coll, xs, dtype="float32", nchannels=C, chunk_bytes=chunk, algo=algo)
             for r in range(R):
-                _assert_bits(got[r], want[r], f"xcd scope {coll} {algo} {proto} R={R} rank {r}")
+                _assert_bits(got[r], want[r], f"device scope {coll} {algo} {proto} R={R} rank {r}")
 
 
-def test_device_scope_is_the_default(vccl, comms_for):
-    comms = comms_for(8)
-    xs = _inputs(8, "int32", 1000)
-    got = _run(vccl, comms, "allreduce", xs, 1000, "int32")
-    assert vccl.vcclCommGetLastPlan(comms[0])["scope"] == 0
-    _assert_bits(got[0], defs.allreduce(xs, "sum", "int32")[0], "device scope")
+@pytest.mark.parametrize("proto", PROTOS)
+def test_xcd_scope_is_the_default_and_reuses_slots_safely(vccl, comms_for, proto):
+    """Default XCD scope (plain stores into the lane's L2, sc1 loads): tiny
+    chunks make every FIFO slot and counter line be rewritten and re-read
+    hundreds of times in one launch, in every algorithm."""
+    R, n = 4, 60001
+    comms = comms_for(R)
+    for coll, algo in (("allreduce", "ring"), ("allreduce", "tree"), ("reducescatter", "ring"),
+                       ("allgather", "ring"), ("broadcast", "ring"), ("reduce", "ring")):
+        xs = _inputs(R, "int32", H.send_len(coll, n, R), extra=77)
+        H.tune(vccl, comms, algo, proto, nchannels=1, chunk=256, direct=1)
+        try:
+            got = _run(vccl, comms, coll, xs, n, "int32", root=2)
+            assert vccl.vcclCommGetLastPlan(comms[0])["scope"] == 1
+        finally:
+            H.untune(vccl, comms)
+        want = sim.run(coll, xs, dtype="int32", nchannels=1, chunk_bytes=256, algo=algo, root=2)
+        for r in range(R):
+            if coll == "reduce" and r != 2:
+                continue
+            _assert_bits(got[r], want[r], f"xcd scope {coll} {algo} {proto} rank {r}")

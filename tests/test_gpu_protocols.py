@@ -56,9 +56,10 @@ def test_fifo_lines_follow_the_paper_format(vccl, proto):
 
 
 def test_ll128_lines_never_tear(vccl):
-    # 4 pairs: writer and reader on different XCDs; 8 pairs: on the same XCD
-    for pairs in (4, 8):
-        torn, checked, res = vccl.vcclProbeLL128Tear(pairs, 2048, 100)
-        assert res == vccl.vcclSuccess
+    # device-scope stores: 4 pairs put writer and reader on different XCDs,
+    # 8 pairs on the same XCD; XCD-scope plain stores: pairs share an XCD
+    for scope, pairs in ((0, 4), (0, 8), (1, 8), (1, 16)):
+        torn, checked, res = vccl.vcclProbeLL128Tear(pairs, 2048, 100, scope)
+        assert res == vccl.vcclSuccess, (scope, pairs)
         assert checked == pairs * 2048 * 100
-        assert torn == 0
+        assert torn == 0, (scope, pairs)
