@@ -1145,6 +1145,7 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
   uint32_t lane, rank;
   if (!claimRole(d.comm, d.xcdMap, d.claimBase, d.perXcd, R, &lane, &rank, &sRole)) return;
   if (lane >= d.nlanes) return;
+  if ((d.comm->deadMask >> rank) & 1u) return;  // test hook: a rank that never shows up
   Ctx c;
   c.comm = d.comm;
   c.rank = (int)rank;
@@ -1183,7 +1184,8 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
         else __builtin_amdgcn_s_sleep(16);
         if ((it & 63u) == 63u) {
           if (ldSystem32(d.stop)) break;
-          if (ldSystem32(d.comm->abortFlag)) break;
+          // an abort, or a failed wait anywhere (timeout): the whole grid leaves
+          if (ldSystem32(d.comm->abortFlag) || ldSystem32(d.comm->errorWord)) break;
           if (leader && nowTicks() - t0 > d.idleTicks) {
             // the whole kernel stops together (a lane whose workgroups left
             // could not run the work the host posts next); the host relaunches

@@ -71,6 +71,20 @@ struct vcclServer {
 
 namespace {
 
+// Releases everything a server holds (null-safe; the kernel has ended).
+void freeServer(vcclServer* s) {
+  if (s->stream) hipStreamDestroy(s->stream);
+  for (auto& kv : s->reqs) delete kv.second;
+  if (s->hQueue) hipHostFree(s->hQueue);
+  if (s->hPosted) hipHostFree(s->hPosted);
+  if (s->hDone) hipHostFree(s->hDone);
+  if (s->hStop) hipHostFree(s->hStop);
+  if (s->hDbg) hipHostFree(s->hDbg);
+  if (s->dMirror) hipFree(s->dMirror);
+  if (s->dLaneSeq) hipFree(s->dLaneSeq);
+  delete s;
+}
+
 uint64_t laneDone(vcclServer* s, int lane) {
   uint64_t m = UINT64_MAX;
   for (int r = 0; r < s->c->nranks; ++r)
@@ -245,6 +259,7 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     logError("serve create", e, __FILE__, __LINE__);
+    freeServer(s);
     return vcclUnhandledHipError;
   }
   memset(s->hQueue, 0, sizeof(ServeEntry) * lanes * SERVE_QUEUE);
@@ -268,6 +283,7 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   vcclResult_t r = launchKernel(s);
   if (r != vcclSuccess) {
     c->serving = false;
+    freeServer(s);
     return r;
   }
   *out = s;
@@ -411,17 +427,8 @@ vcclResult_t vcclServeDestroy(vcclServer_t s) {
   while ((!s->waiting.empty() || !s->inflight.empty()) && nowNs() < deadline) progress(s);
   __atomic_store_n(s->hStop, 1u, __ATOMIC_RELEASE);
   hipStreamSynchronize(s->stream);
-  hipStreamDestroy(s->stream);
-  for (auto& kv : s->reqs) delete kv.second;
-  hipHostFree(s->hQueue);
-  hipHostFree(s->hPosted);
-  hipHostFree(s->hDone);
-  hipHostFree(s->hStop);
-  hipHostFree(s->hDbg);
-  hipFree(s->dMirror);
-  hipFree(s->dLaneSeq);
   c->serving = false;
-  delete s;
+  freeServer(s);
   return vcclSuccess;
 }
 

@@ -153,3 +153,40 @@ def test_poisson_replay_reports_latencies(vccl):
     finally:
         for c in comms:
             vccl.vcclCommDestroy(c)
+
+
+def test_dead_rank_fails_requests_in_bounded_time(vccl):
+    """A rank whose workgroups never show up (test hook) with a 20 ms wait
+    limit: the request completes with RemoteError, later submissions fail at
+    once, the whole persistent grid leaves, and the server is destroyed."""
+    import time
+    t = H.torch()
+    R = 4
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        vccl.vcclCommSetTimeout(comms[0], 20000)
+        vccl.vcclCommDebugSetDeadRanks(comms[0], 1 << 2)
+        xs = [t.ones(4096, device="cuda") for _ in range(R)]
+        t.cuda.synchronize()
+        srv = vccl.vcclServeCreate(comms, 1 << 30, 4)
+        try:
+            t0 = time.time()
+            rid = vccl.vcclServeSubmit(srv, 0, vccl.vcclFloat32, vccl.vcclSum, 0, 4096, xs, xs)
+            status = None
+            while time.time() - t0 < 30:
+                done, status, _ = vccl.vcclServeTest(srv, rid)
+                if done:
+                    break
+            assert status == vccl.vcclRemoteError
+            assert time.time() - t0 < 30
+            rid = vccl.vcclServeSubmit(srv, 0, vccl.vcclFloat32, vccl.vcclSum, 0, 4096, xs, xs)
+            done, status, _ = vccl.vcclServeTest(srv, rid)
+            assert done and status == vccl.vcclRemoteError
+        finally:
+            t0 = time.time()
+            vccl.vcclServeDestroy(srv)
+            assert time.time() - t0 < 10
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclRemoteError
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
