@@ -912,27 +912,38 @@ __device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args
 // software-pipelined: the upward step of chunk j precedes the downward step
 // of chunk j - (NSLOTS - 1), which cannot deadlock with NSLOTS slots.
 template <int PROTO, int SC, int DT, int OP>
-__device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+__device__ void treeAllReduce(const Ctx& c0, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+  // A channel runs fused (one workgroup per rank takes both phases, the
+  // downward step of iteration j - lag after the upward step of iteration j)
+  // or split: the up half and the down half run on two lanes of one XCD at
+  // once, both addressing the connections of the up half's lane.
+  if (w.role == ROLE_IDLE) return;
+  Ctx c = c0;
+  if (w.role != ROLE_FUSED) c.lane = w.connLane;
+  const bool up = w.role != ROLE_DOWN, down = w.role != ROLE_UP;
   const int me = c.rank, t = w.tree;
   const int par = c.comm->parent[t][me];
   const int nk = c.comm->nchild[t][me];
   const int k0 = c.comm->child[t][me][0], k1 = c.comm->child[t][me][1];
+  if (!up && par < 0) return;  // the root's downward sends belong to its upward step
   // receive side: 0,1 up from children; 2 down from parent
-  const int rk[3] = {nk > 0 ? 1 + 3 * t : -1, nk > 1 ? 2 + 3 * t : -1, par >= 0 ? 3 + 3 * t : -1};
-  // send side: 0 up to parent; 1,2 down to children
-  const int sp[3] = {par, nk > 0 ? k0 : -1, nk > 1 ? k1 : -1};
-  const int sk[3] = {par >= 0 ? 1 + 3 * t + c.comm->childIdx[t][me] : -1, 3 + 3 * t, 3 + 3 * t};
+  const int rk[3] = {up && nk > 0 ? 1 + 3 * t : -1, up && nk > 1 ? 2 + 3 * t : -1,
+                     down && par >= 0 ? 3 + 3 * t : -1};
+  // send side: 0 up to parent; 1,2 down to children (the root's in its upward step)
+  const bool sendsDown = down || par < 0;
+  const int sp[3] = {up ? par : -1, sendsDown && nk > 0 ? k0 : -1, sendsDown && nk > 1 ? k1 : -1};
+  const int sk[3] = {up && par >= 0 ? 1 + 3 * t + c.comm->childIdx[t][me] : -1, 3 + 3 * t, 3 + 3 * t};
   Conn r[3], s[3];
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const int upR = (nk > 0 ? 1 : 0) | (nk > 1 ? 2 : 0);
   const int downS = (nk > 0 ? 2 : 0) | (nk > 1 ? 4 : 0);
   const uint64_t E = w.elemBytes, K = w.chunk;
   const uint64_t nch = ceilDiv(w.chCount, K);
-  const uint64_t lag = NSLOTS - 1;
+  const uint64_t lag = (up && down) ? NSLOTS - 1 : 0;
   const char* sendb = args.send[me];
   char* recvb = args.recv[me];
   for (uint64_t j = 0; j < nch + lag; ++j) {
-    if (j < nch) {
+    if (up && j < nch) {
       const uint64_t a0 = j * K, len = umin(K, w.chCount - a0);
       const uint64_t off = (w.chOffset + a0) * E;
       StepArgs a{};
@@ -947,7 +958,7 @@ __device__ void treeAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
       }
       if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
     }
-    if (j >= lag && par >= 0) {
+    if (down && j >= lag && par >= 0) {
       const uint64_t jd = j - lag, a0 = jd * K, len = umin(K, w.chCount - a0);
       const uint64_t off = (w.chOffset + a0) * E;
       StepArgs a{};

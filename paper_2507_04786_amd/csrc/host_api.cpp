@@ -81,7 +81,7 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
 
   std::vector<Plan> plans(colls.size());
   for (size_t g = 0; g < colls.size(); ++g) {
-    vcclResult_t r = planColl(c, colls[g], &plans[g]);
+    vcclResult_t r = planColl(c, colls[g], &plans[g], colls.size() == 1);
     if (r != vcclSuccess) return r;
     if (plans[g].algo == ALGO_TREE) {
       r = cliqueEnsureTreeFifos(c);
@@ -124,6 +124,23 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   if (colls.size() == 1 && plans[0].nchannels <= MAX_INLINE) {
     std::vector<WorkItem> items;
     fillItems(c, colls[0], plans[0], 0, 0, &items);
+    if (plans[0].split) {
+      // channel ch: up half on lane ch, down half on lane off + ch (same XCD:
+      // off is a multiple of 8); lanes between the two groups stay idle
+      const int C = (int)items.size(), off = 8 * ((C + 7) / 8);
+      std::vector<WorkItem> byLane((size_t)(off + C));
+      for (int l = 0; l < off; ++l) {
+        byLane[l] = items[l < C ? l : 0];
+        byLane[l].role = l < C ? ROLE_UP : ROLE_IDLE;
+        byLane[l].connLane = (uint8_t)l;
+      }
+      for (int ch = 0; ch < C; ++ch) {
+        byLane[off + ch] = items[ch];
+        byLane[off + ch].role = ROLE_DOWN;
+        byLane[off + ch].connLane = (uint8_t)ch;
+      }
+      items.swap(byLane);
+    }
     d.items = nullptr;
     d.inlineArgs = colls[0].args;
     for (size_t i = 0; i < items.size(); ++i) d.inlineItems[i] = items[i];

@@ -201,6 +201,7 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   // written back on eviction); smaller and latency-bound ones up to 9 % (LL,
   // LL128: up to 25 %) faster in XCD scope.
   c->deviceScopeBytes = (uint64_t)envLong("VCCL_DEVICE_SCOPE_BYTES", 8 << 20);
+  c->treeSplit = envLong("VCCL_TREE_SPLIT", 1) != 0;
   if (c->xcdMap && envStr("VCCL_SCOPE") != "device") {
     c->host.scope = SCOPE_XCD;
     e = hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice);

@@ -59,6 +59,7 @@ struct Plan {
   int algo, proto, nchannels, nthreads, direct;
   uint64_t chunkBytes;
   int scope = SCOPE_DEVICE;
+  bool split = false;  // tree channels run as concurrent up and down halves on two lanes
 };
 
 struct Tuning {
@@ -109,6 +110,7 @@ struct Clique {
   int occupancy[17] = {0};    // blocks per CU for nthreads = 64 * index
   bool serving = false;       // a persistent serving kernel owns the lanes
   uint64_t deviceScopeBytes = 0;  // Simple items of collectives this large use device scope
+  bool treeSplit = true;          // split Simple tree channels into concurrent halves
   uint64_t* claim = nullptr;  // per-XCD role counters (device)
   uint64_t claimBase = 0;     // role claims of all launches so far, per XCD
 };
@@ -128,7 +130,8 @@ void buildTrees(int nranks, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RAN
 // host_plan.cpp
 size_t dtypeBytes(int dtype);
 uint64_t collSizeBytes(uint8_t coll, size_t count, int dtype, int nranks);
-vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan);
+// single: the collective is launched alone (a tree may then be split).
+vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single = false);
 // Channel regions [start, end) in units: per = roundUp(ceil(n / C), align).
 void channelRange(uint64_t n, int nchannels, uint64_t align, int ch, uint64_t* start, uint64_t* count);
 void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t argsIndex, uint32_t doneIndex,

@@ -109,7 +109,7 @@ static vcclResult_t planP2p(Clique* c, const Coll& coll, Plan* plan) {
   return vcclSuccess;
 }
 
-vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
+vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   if (coll.coll == COLL_SENDRECV) return planP2p(c, coll, plan);
   const int R = c->nranks;
   const uint64_t S = collSizeBytes(coll.coll, coll.count, coll.dtype, R);
@@ -135,6 +135,11 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   dfltC = std::max(1L, std::min<long>(dfltC, laneCap));
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));
+  // --- a Simple tree launched alone runs each channel as two concurrent
+  // halves (reduce-up and broadcast-down) on two lanes of one XCD; the pair
+  // of lanes fits the inline launch with up to 16 channels
+  bool split = single && c->treeSplit && c->xcdMap && algo == ALGO_TREE && proto == PROTO_SIMPLE;
+  if (split) nch = std::min(nch, 16);
   // --- workgroup size
   long dfltT = (S >= (256u << 10)) ? 512 : 256;
   if (proto == PROTO_SIMPLE) dfltT = 256;
@@ -146,6 +151,8 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   if (c->xcdMap) {
     // the XCD map launches 8 * R * ceil(L / 8) workgroups
     while (nch > 1 && 8 * R * (int)ceilDiv(nch, 8) > c->numCUs * occ) --nch;
+    // a split tree takes 8 ceil(C / 8) + C lanes
+    if (split && 8 * R * (int)ceilDiv(8 * ceilDiv(nch, 8) + nch, 8) > c->numCUs * occ) split = false;
   } else {
     nch = std::min(nch, std::max(1, (c->numCUs * occ) / R));
   }
@@ -180,6 +187,8 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan) {
   plan->nthreads = nthreads;
   plan->direct = direct;
   plan->chunkBytes = chunk;
+  // halves pay off once a channel pipelines at least two chunks
+  plan->split = split && ceilDiv(ceilDiv(S, (uint64_t)nch), chunk) >= 2;
   // store policy: XCD scope (lower latency) unless a large Simple transfer
   plan->scope = (c->host.scope == SCOPE_XCD && !(proto == PROTO_SIMPLE && S >= c->deviceScopeBytes))
                     ? SCOPE_XCD : SCOPE_DEVICE;

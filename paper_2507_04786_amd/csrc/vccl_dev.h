@@ -80,7 +80,9 @@ struct WorkItem {
   uint32_t unitBytes;        // 1 (AllGather, Broadcast) or the element size
   uint32_t elemBytes;
   uint8_t scope;             // SCOPE_DEVICE or SCOPE_XCD: store policy of this item's traffic
-  uint8_t pad[3];
+  uint8_t role;              // tree: ROLE_FUSED, or the up / down half of a split channel, or idle
+  uint8_t connLane;          // tree halves: the lane whose connections both halves use
+  uint8_t pad;
   uint64_t count;            // units per rank (per block for AllGather / ReduceScatter)
   uint64_t chOffset;         // workOffset of this channel, units
   uint64_t chCount;          // channelCount, units
@@ -88,6 +90,7 @@ struct WorkItem {
 };
 
 static_assert(sizeof(WorkItem) == 64, "work items are 64 bytes");
+enum : uint8_t { ROLE_FUSED = 0, ROLE_UP = 1, ROLE_DOWN = 2, ROLE_IDLE = 3 };
 
 struct CollArgs {
   const char* send[MAX_RANKS];

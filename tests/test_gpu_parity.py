@@ -189,6 +189,42 @@ def test_default_plans_match_oracle(vccl, comms_for, R):
                     _assert_bits(got[r], xs[root], f"{what} rank {r}")
 
 
+@pytest.mark.parametrize("split", [True, False])
+def test_tree_halves_and_fused_channels(vccl, comms_for, split):
+    """A Simple tree launched alone runs each channel as concurrent up and
+    down halves on two lanes (VCCL_TREE_SPLIT=0: one fused workgroup per rank
+    and channel); both give the oracle's bits for every dtype and op."""
+    import os
+    old = os.environ.get("VCCL_TREE_SPLIT")
+    os.environ["VCCL_TREE_SPLIT"] = "1" if split else "0"
+    try:
+        for R in (4, 8, 16):
+            comms = vccl.vcclCommInitAll(R)
+            try:
+                for dtype, op, n, C, chunk in (("float32", "sum", 100003, 3, 4096), ("bfloat16", "sum", 50001, 8, 2048),
+                                               ("int32", "max", 70001, 16, 1024)):
+                    xs = _inputs(R, dtype, n, wl=3, extra=R + C)
+                    H.tune(vccl, comms, "tree", "simple", nchannels=C, chunk=chunk)
+                    try:
+                        got = _run(vccl, comms, "allreduce", xs, n, dtype, op)
+                        info = vccl.vcclCommGetLastPlan(comms[0])
+                    finally:
+                        H.untune(vccl, comms)
+                    lanes = 8 * ((C + 7) // 8) + C if split else C
+                    assert info["nlanes"] == lanes, (R, C, info)
+                    want = folds.tree_allreduce(xs, op, dtype, C)
+                    for r in range(R):
+                        _assert_bits(got[r], want, f"tree split={split} {dtype} {op} R={R} C={C} rank {r}")
+            finally:
+                for c in comms:
+                    vccl.vcclCommDestroy(c)
+    finally:
+        if old is None:
+            del os.environ["VCCL_TREE_SPLIT"]
+        else:
+            os.environ["VCCL_TREE_SPLIT"] = old
+
+
 @pytest.mark.parametrize("coll", ["allreduce", "allgather", "broadcast"])
 def test_direct_variants_match(vccl, comms_for, coll):
     """P2P_DIRECT-style copies give the same bits as the FIFO path."""
