@@ -196,6 +196,9 @@ typedef struct {
   int scope;          /* store policy chosen for the (first) collective: 0 device-coherent
                          stores, 1 plain stores into the XCD's L2 (each channel's
                          workgroups share an XCD; loads are device-coherent in both) */
+  int treeRanksPerNode; /* tree topology of the set (VCCL_TREE_RANKS_PER_NODE at init):
+                           chains of this many consecutive ranks, double binary tree
+                           across the chains; 1 = the plain double binary tree */
 } vcclPlanInfo_t;
 vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info);
 

@@ -92,11 +92,11 @@ def ring_reduce(xs, op, dtype, root, idx=None):
     return _fold([np.asarray(xs[q])[idx] for q in order], op, dtype)
 
 
-def tree_allreduce(xs, op, dtype, nchannels, idx=None):
+def tree_allreduce(xs, op, dtype, nchannels, idx=None, ranks_per_node=1):
     R = len(xs)
     n = len(xs[0])
     A = pt.align_units("allreduce", ew.ELEM_BYTES[dtype])
-    trees = topo.double_binary_tree(R)
+    trees = topo.double_binary_tree(R, ranks_per_node)
     if idx is None:
         idx = np.arange(n)
     idx = np.asarray(idx, dtype=np.int64)

@@ -301,12 +301,12 @@ def ring_reduce(xs, root, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trac
     return [out if p == root else None for p in range(R)]
 
 
-def tree_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, lag=0, trace=None):
+def tree_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, lag=0, trace=None, ranks_per_node=1):
     """Double-binary-tree AllReduce; channel c uses tree c mod 2."""
     R = len(xs)
     n = len(xs[0])
     A = pt.align_units("allreduce", ew.ELEM_BYTES[dtype])
-    trees = topo.double_binary_tree(R)
+    trees = topo.double_binary_tree(R, ranks_per_node)
     outs = [np.zeros_like(x) for x in xs]
     if lag < 0:
         raise ValueError("lag must be >= 0")
@@ -349,7 +349,7 @@ def tree_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, lag=0, 
 
 
 def run(coll, xs, *, op="sum", dtype, nchannels=1, chunk_bytes, root=0, algo="ring",
-        slots=DEFAULT_SLOTS, lag=0, trace=None):
+        slots=DEFAULT_SLOTS, lag=0, trace=None, ranks_per_node=1):
     """Dispatch by collective name; chunk_bytes is converted to partition units."""
     E = ew.ELEM_BYTES[dtype]
     ub = pt.unit_bytes(coll, E)
@@ -358,7 +358,7 @@ def run(coll, xs, *, op="sum", dtype, nchannels=1, chunk_bytes, root=0, algo="ri
     K = chunk_bytes // ub
     if coll == "allreduce":
         if algo == "tree":
-            return tree_allreduce(xs, op, dtype, nchannels, K, slots, lag, trace)
+            return tree_allreduce(xs, op, dtype, nchannels, K, slots, lag, trace, ranks_per_node)
         return ring_allreduce(xs, op, dtype, nchannels, K, slots, trace)
     if coll == "reducescatter":
         return ring_reducescatter(xs, op, dtype, nchannels, K, slots, trace)

@@ -70,8 +70,13 @@ def _positions_tree(nranks: int):
     return parent, children
 
 
-def double_binary_tree(nranks: int):
-    """Returns [treeA, treeB]; each is dict(parent=[...], children=[[...]...]) indexed by rank."""
+def double_binary_tree(nranks: int, ranks_per_node: int = 1):
+    """Returns [treeA, treeB]; each is dict(parent=[...], children=[[...]...]) indexed by rank.
+
+    ranks_per_node > 1: chains within a node, the double binary tree across
+    nodes (see chain_tree)."""
+    if ranks_per_node > 1:
+        return chain_tree(nranks, ranks_per_node)
     pparent, pchildren = _positions_tree(nranks)
     trees = []
     for which in (0, 1):
@@ -102,3 +107,43 @@ def tree_depth(tree) -> int:
             d += 1
         best = max(best, d)
     return best
+
+
+def chain_tree(nranks: int, ranks_per_node: int):
+    """Trees that branch only across nodes and form a chain within a node
+    (Section V-E, tree AllReduce).  Ranks n*P .. n*P+P-1 form node n
+    (P = ranks_per_node, which must divide nranks).  Reading adopted (the
+    paper does not say where the inter-node links attach):
+
+    * the nodes form the double binary tree over node indices;
+    * within node n the chain runs, for tree A, local 0 <- local 1 <- ... <-
+      local P-1 (local 0 is the head) and, for tree B, the reverse (local P-1
+      is the head);
+    * a node's head sends to its parent node; the parent node takes its first
+      node child at its head and its second at the next rank of its chain,
+      so no rank has more than two children;
+    * at a rank the chain child comes first, then the node child.
+    """
+    P = ranks_per_node
+    if P < 1 or nranks % P:
+        raise ValueError("ranks_per_node must divide nranks")
+    N = nranks // P
+    node_trees = double_binary_tree(N)
+    trees = []
+    for which in (0, 1):
+        nt = node_trees[which]
+        order = [[n * P + k for k in (range(P) if which == 0 else range(P - 1, -1, -1))] for n in range(N)]
+        parent = [-1] * nranks
+        children: list[list[int]] = [[] for _ in range(nranks)]
+        for n in range(N):
+            for i in range(1, P):
+                parent[order[n][i]] = order[n][i - 1]
+                children[order[n][i - 1]].append(order[n][i])
+        for n in range(N):
+            for j, m in enumerate(nt["children"][n]):
+                at = order[n][j]
+                parent[order[m][0]] = at
+                children[at].append(order[m][0])
+        trees.append(dict(parent=parent, children=children, root=order[nt["root"]][0]))
+    return trees
+

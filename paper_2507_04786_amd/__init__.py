@@ -58,7 +58,7 @@ class vcclTuning_t(C.Structure):
 class vcclPlanInfo_t(C.Structure):
     _fields_ = [("algo", C.c_int), ("proto", C.c_int), ("nchannels", C.c_int), ("nthreads", C.c_int),
                 ("direct", C.c_int), ("nlanes", C.c_int), ("nitems", C.c_int), ("ncolls", C.c_int),
-                ("chunkBytes", C.c_size_t), ("grid", C.c_int), ("scope", C.c_int)]
+                ("chunkBytes", C.c_size_t), ("grid", C.c_int), ("scope", C.c_int), ("treeRanksPerNode", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

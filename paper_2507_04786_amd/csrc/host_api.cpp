@@ -221,6 +221,7 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   info.ncolls = (int)colls.size();
   info.grid = grid;
   info.scope = plans[0].scope;
+  info.treeRanksPerNode = c->ranksPerNode;
   (void)grouped;
   return vcclSuccess;
 }

@@ -49,8 +49,42 @@ long envLong(const char* name, long dflt) {
 // largest power of two below R; position q (lowest set bit b) has parent
 // (q - b) | 2b, or q - b when that is >= R; its children are q - b/2 and the
 // first of q + b/2, q + b/4, ..., q + 1 below R.
-void buildTrees(int R, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2], int8_t childIdx[2][MAX_RANKS],
-                int8_t nchild[2][MAX_RANKS]) {
+// ranksPerNode P > 1: node n = ranks n*P .. n*P+P-1 forms a chain (tree 0:
+// local 0 <- 1 <- ... <- P-1, tree 1 the reverse), the nodes form the double
+// binary tree, a node's chain head sends to its parent node, which takes its
+// first node child at its head and its second at the next rank of its chain
+// (at most two children per rank; the chain child first).
+void buildTrees(int R, int ranksPerNode, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2],
+                int8_t childIdx[2][MAX_RANKS], int8_t nchild[2][MAX_RANKS]) {
+  if (ranksPerNode > 1 && R % ranksPerNode == 0) {
+    const int P = ranksPerNode, N = R / P;
+    int8_t np[2][MAX_RANKS], nc[2][MAX_RANKS][2], nci[2][MAX_RANKS], nn[2][MAX_RANKS];
+    buildTrees(N, 1, np, nc, nci, nn);
+    for (int t = 0; t < 2; ++t) {
+      auto at = [&](int node, int pos) { return node * P + (t == 0 ? pos : P - 1 - pos); };
+      for (int r = 0; r < R; ++r) {
+        parent[t][r] = -1;
+        nchild[t][r] = 0;
+        child[t][r][0] = child[t][r][1] = -1;
+      }
+      for (int n = 0; n < N; ++n)
+        for (int i = 1; i < P; ++i) {
+          parent[t][at(n, i)] = (int8_t)at(n, i - 1);
+          child[t][at(n, i - 1)][nchild[t][at(n, i - 1)]++] = (int8_t)at(n, i);
+        }
+      for (int n = 0; n < N; ++n)
+        for (int j = 0; j < nn[t][n]; ++j) {
+          const int m = nc[t][n][j], where = at(n, j);
+          parent[t][at(m, 0)] = (int8_t)where;
+          child[t][where][nchild[t][where]++] = (int8_t)at(m, 0);
+        }
+      for (int r = 0; r < R; ++r)
+        for (int k = 0; k < nchild[t][r]; ++k) childIdx[t][child[t][r][k]] = (int8_t)k;
+      for (int r = 0; r < R; ++r)
+        if (parent[t][r] < 0) childIdx[t][r] = 0;
+    }
+    return;
+  }
   int pPar[MAX_RANKS], pKids[MAX_RANKS][2], pN[MAX_RANKS];
   for (int q = 0; q < R; ++q) {
     pPar[q] = -1;
@@ -159,7 +193,14 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   c->host.errorWord = c->hError;
   memset(c->host.parent, -1, sizeof(c->host.parent));
   memset(c->host.child, -1, sizeof(c->host.child));
-  buildTrees(nranks, c->host.parent, c->host.child, c->host.childIdx, c->host.nchild);
+  // tree topology: VCCL_TREE_RANKS_PER_NODE groups consecutive ranks into
+  // "nodes" (chains within a node, the double binary tree across them)
+  c->ranksPerNode = (int)envLong("VCCL_TREE_RANKS_PER_NODE", 1);
+  if (c->ranksPerNode < 1 || c->ranksPerNode > nranks || nranks % c->ranksPerNode) {
+    logInfo("VCCL_TREE_RANKS_PER_NODE=%d does not divide %d ranks; using 1", c->ranksPerNode, nranks);
+    c->ranksPerNode = 1;
+  }
+  buildTrees(nranks, c->ranksPerNode, c->host.parent, c->host.child, c->host.childIdx, c->host.nchild);
   e = hipMalloc((void**)&c->dcomm, sizeof(DevComm));
   if (e != hipSuccess) return fail(e, "hipMalloc(devcomm)");
   e = hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice);

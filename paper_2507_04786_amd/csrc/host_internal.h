@@ -111,6 +111,7 @@ struct Clique {
   bool serving = false;       // a persistent serving kernel owns the lanes
   uint64_t deviceScopeBytes = 0;  // Simple items of collectives this large use device scope
   bool treeSplit = true;          // split Simple tree channels into concurrent halves
+  int ranksPerNode = 1;           // tree topology: chains of this many ranks, trees across them
   uint64_t* claim = nullptr;  // per-XCD role counters (device)
   uint64_t claimBase = 0;     // role claims of all launches so far, per XCD
 };
@@ -124,7 +125,7 @@ void cliqueFree(Clique* c);
 vcclResult_t cliqueEnsureTreeFifos(Clique* c);
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps);
 int cliqueOccupancy(Clique* c, int nthreads);
-void buildTrees(int nranks, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2],
+void buildTrees(int nranks, int ranksPerNode, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2],
                 int8_t childIdx[2][MAX_RANKS], int8_t nchild[2][MAX_RANKS]);
 
 // host_plan.cpp

@@ -225,6 +225,42 @@ def test_tree_halves_and_fused_channels(vccl, comms_for, split):
             os.environ["VCCL_TREE_SPLIT"] = old
 
 
+@pytest.mark.parametrize("R,P", [(4, 2), (8, 2), (8, 4), (16, 4), (16, 8), (12, 3)])
+def test_chain_tree_topology(vccl, R, P):
+    """VCCL_TREE_RANKS_PER_NODE=P: chains within groups of P ranks, the double
+    binary tree across them; every protocol, split and fused channels, sum and
+    max, against the oracle's fold on the same topology."""
+    import os
+    old = os.environ.get("VCCL_TREE_RANKS_PER_NODE")
+    os.environ["VCCL_TREE_RANKS_PER_NODE"] = str(P)
+    try:
+        comms = vccl.vcclCommInitAll(R)
+    finally:
+        if old is None:
+            del os.environ["VCCL_TREE_RANKS_PER_NODE"]
+        else:
+            os.environ["VCCL_TREE_RANKS_PER_NODE"] = old
+    try:
+        for proto, dtype, op, n, C, chunk in (("simple", "float32", "sum", 40001, 4, 1024),
+                                              ("ll", "bfloat16", "sum", 9001, 3, 0),
+                                              ("ll128", "float32", "sum", 30001, 2, 0),
+                                              ("simple", "int32", "max", 5001, 1, 512)):
+            xs = _inputs(R, dtype, n, wl=3, extra=R * 10 + P)
+            H.tune(vccl, comms, "tree", proto, nchannels=C, chunk=chunk)
+            try:
+                got = _run(vccl, comms, "allreduce", xs, n, dtype, op)
+                info = vccl.vcclCommGetLastPlan(comms[0])
+            finally:
+                H.untune(vccl, comms)
+            assert info["treeRanksPerNode"] == P and info["algo"] == 1
+            want = folds.tree_allreduce(xs, op, dtype, C, ranks_per_node=P)
+            for r in range(R):
+                _assert_bits(got[r], want, f"chain tree R={R} P={P} {proto} {dtype} {op} rank {r}")
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+
+
 @pytest.mark.parametrize("coll", ["allreduce", "allgather", "broadcast"])
 def test_direct_variants_match(vccl, comms_for, coll):
     """P2P_DIRECT-style copies give the same bits as the FIFO path."""

@@ -414,8 +414,8 @@ def test_pins_catch_wrong_segment_index(monkeypatch):
 def test_pins_catch_swapped_tree_children(monkeypatch):
     orig = topo.double_binary_tree
 
-    def swapped(R):
-        trees = orig(R)
+    def swapped(R, ranks_per_node=1):
+        trees = orig(R, ranks_per_node)
         for t in trees:
             t["children"] = [list(reversed(c)) for c in t["children"]]
         return trees
