@@ -53,8 +53,23 @@ __device__ __forceinline__ void orSystem32(uint32_t* p, uint32_t v) {
 __device__ __forceinline__ void drainVmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 __device__ __forceinline__ uint64_t nowTicks() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Workgroup-uniform values (stream bases, sizes, strides) often reach the
+// code that uses them through LDS, memory or a call, where the compiler can
+// no longer tell they are uniform: it keeps them in vector registers and
+// wraps every buffer access in a loop over the distinct values of the wave.
+// Taking lane 0's copy makes them scalar; callers pass only uniform values.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+template <class T>
+__device__ __forceinline__ T* uniformPtr(T* p) { return (T*)uniform64((uint64_t)p); }
+
+// Buffer resource over [base, base + bytes): accesses past the end read zero
+// and write nothing.  base and bytes must be uniform over the wave.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t makeRsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uniformPtr(base)), (short)0, (int)uniform(bytes),
+                                           0x00020000);
 }
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -220,6 +235,33 @@ struct Ctx {
   int* sAbort;  // LDS flag: set when any wait of this workgroup failed
 };
 
+// Scalar copies of the workgroup-uniform state a work item runs on (the
+// context, the item's words, read from LDS or through a call): every pointer,
+// size and loop bound derived from them then stays in scalar registers.
+__device__ __forceinline__ Ctx uniformCtx(const Ctx& c0) {
+  Ctx c;
+  c.comm = uniformPtr(c0.comm);
+  c.rank = (int)uniform((uint32_t)c0.rank);
+  c.lane = (int)uniform((uint32_t)c0.lane);
+  c.nranks = (int)uniform((uint32_t)c0.nranks);
+  c.nthreads = (int)uniform((uint32_t)c0.nthreads);
+  c.nwaves = (int)uniform((uint32_t)c0.nwaves);
+  c.wave = (int)uniform((uint32_t)c0.wave);
+  c.tid = c0.tid;
+  c.lid = c0.lid;
+  c.sAbort = uniformPtr(c0.sAbort);
+  return c;
+}
+__device__ __forceinline__ WorkItem uniformItem(const WorkItem& w0) {
+  uint32_t words[sizeof(WorkItem) / 4];
+  __builtin_memcpy(words, &w0, sizeof(WorkItem));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(WorkItem) / 4); ++i) words[i] = uniform(words[i]);
+  WorkItem w;
+  __builtin_memcpy(&w, words, sizeof(WorkItem));
+  return w;
+}
+
 struct Conn {
   char* fifo = nullptr;       // this connection's FIFO for the current protocol
   uint64_t* tail = nullptr;
@@ -234,7 +276,7 @@ __device__ __forceinline__ uint64_t creditTarget(uint64_t step) { return step + 
 // Bounded wait for *ctr >= target, one lane.  Returns false (and records the
 // error) on timeout or abort.
 template <int SC>
-__device__ __noinline__ bool waitCounter(const Ctx& c, const uint64_t* ctr, uint64_t target) {
+__device__ __forceinline__ bool waitCounter(const Ctx& c, const uint64_t* ctr, uint64_t target) {
   if (ldCtr<SC>(ctr) >= target) return true;
   uint64_t t0 = nowTicks();
   uint32_t it = 0;
@@ -298,7 +340,7 @@ template <int DT, int OP, int NIN, int NOUT, int LP, int SP>
 __device__ __forceinline__ void reduceCopyVec(const Ctx& c, const PtrList& in, const PtrList& out, uint32_t nvec) {
   constexpr int U = 4;
   const uint32_t nb = nvec * 16;
-  const uint32_t stride = (uint32_t)c.nthreads * 16;
+  const uint32_t stride = uniform((uint32_t)c.nthreads * 16);
   const __amdgpu_buffer_rsrc_t i0 = makeRsrc(in.p0, nb);
   const __amdgpu_buffer_rsrc_t i1 = makeRsrc(in.p1, nb);
   const __amdgpu_buffer_rsrc_t i2 = makeRsrc(in.p2, nb);
@@ -353,8 +395,23 @@ __device__ __forceinline__ void reduceCopyPart(const Ctx& c, const PtrList& in, 
 
 // Loads of every stream are sc1; stores follow the scope (sc1 for
 // SCOPE_DEVICE, plain for SCOPE_XCD).
+// Arguments by value: they travel in registers, where a reference would make
+// the caller store the lists to its stack for every step.
 template <int DT, int OP, int NIN, int NOUT, int SC>
-__device__ __noinline__ void reduceCopy(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
+__device__ __noinline__ void reduceCopy(int tid, int nthreads, const char* i0, const char* i1, const char* i2,
+                                        const char* o0, const char* o1, const char* o2, uint64_t nbytes) {
+  Ctx c{};
+  c.tid = tid;
+  c.nthreads = nthreads;
+  PtrList in, out;
+  in.p0 = i0;
+  in.p1 = i1;
+  in.p2 = i2;
+  in.n = NIN;
+  out.p0 = o0;
+  out.p1 = o1;
+  out.p2 = o2;
+  out.n = NOUT;
   const uint32_t nvec = (uint32_t)(nbytes / 16);
   reduceCopyVec<DT, OP, NIN, NOUT, LOAD_AUX, StoreAux<SC>::value>(c, in, out, nvec);
   if (nbytes % 16) reduceCopyPart<DT, OP, NIN, NOUT, SC == SCOPE_DEVICE>(c, in, out, (uint64_t)nvec * 16, nbytes);
@@ -364,7 +421,10 @@ template <int DT, int OP, int SC>
 __device__ void reduceCopyN(const Ctx& c, const PtrList& in, const PtrList& out, uint64_t nbytes) {
   if (nbytes == 0 || in.n == 0 || out.n == 0) return;
 #define VCCL_RC(I, O) \
-  if (in.n == I && out.n == O) { reduceCopy<DT, OP, I, O, SC>(c, in, out, nbytes); return; }
+  if (in.n == I && out.n == O) {                                                                        \
+    reduceCopy<DT, OP, I, O, SC>(c.tid, c.nthreads, in.p0, in.p1, in.p2, out.p0, out.p1, out.p2, nbytes); \
+    return;                                                                                               \
+  }
   VCCL_RC(1, 1) VCCL_RC(1, 2) VCCL_RC(1, 3) VCCL_RC(2, 1) VCCL_RC(2, 2) VCCL_RC(2, 3) VCCL_RC(3, 1) VCCL_RC(3, 2)
   VCCL_RC(3, 3)
 #undef VCCL_RC
@@ -480,11 +540,18 @@ __device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, i
 }
 
 // ------------------------------------------------------------------ LL datapath
-// A lane handles a pair of 8-byte units (8 payload bytes, 16 FIFO bytes).
+// A lane handles LL_UNROLL pairs of 8-byte units (8 payload bytes, 16 FIFO
+// bytes each) per pass, nthreads pairs apart so that a wave's accesses stay
+// contiguous.  All loads of a pass are issued before any flag is checked: a
+// receive is a round trip to memory, and one pair in flight per lane leaves
+// the step latency-bound.
+
+constexpr int LL_UNROLL = 4;
 
 template <int SC, int DT, int OP>
 __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   constexpr int E = ElemSize<DT>::value;
+  constexpr int U = LL_UNROLL;
   if (!waitCredits<SC>(c, s, a.smask)) return false;
   const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL];
   const uint64_t npairs = (a.nbytes + 7) / 8;
@@ -500,55 +567,86 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   const __amdgpu_buffer_rsrc_t bsrc = makeRsrc(a.src, (uint32_t)a.nbytes);
   const __amdgpu_buffer_rsrc_t bdst = makeRsrc(a.dst, (uint32_t)a.nbytes);
   const bool writeDst = a.dst && !(a.src == a.dst && a.rmask == 0);
+  const uint64_t stride = (uint64_t)c.nthreads;
   bool alive = true;
-  for (uint64_t p = c.tid; p < npairs; p += c.nthreads) {
-    const uint64_t off = p * 8;
-    const int valid = (int)((a.nbytes - off) < 8 ? (a.nbytes - off) : 8);
-    uint32_t acc[2] = {0, 0};
-    bool have = false;
-    if (a.src) {
-      if (valid == 8) {
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)off, 0, LOAD_AUX);
-        acc[0] = v.x;
-        acc[1] = v.y;
-      } else {
-        loadPart<E, 2, true>(a.src + off, valid, acc);
+  for (uint64_t p0 = c.tid; p0 < npairs; p0 += stride * U) {
+    uint32_t acc[U][2];
+    int valid[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t p = p0 + stride * u;
+      const uint64_t off = p * 8;
+      valid[u] = p < npairs ? (int)((a.nbytes - off) < 8 ? (a.nbytes - off) : 8) : 0;
+      acc[u][0] = acc[u][1] = 0;
+      if (a.src) {
+        if (valid[u] == 8) {
+          const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)off, 0, LOAD_AUX);
+          acc[u][0] = v.x;
+          acc[u][1] = v.y;
+        } else if (valid[u] > 0) {
+          loadPart<E, 2, true>(a.src + off, valid[u], acc[u]);
+        }
       }
-      have = true;
     }
+    bool have = a.src != nullptr;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       if (alive && (a.rmask & (1 << i))) {
         const uint32_t flag = (uint32_t)(r[i].step + 1);
-        const uint32_t uoff = (uint32_t)p * 16;
-        uint64_t u0 = ldUnit<SC>(rin[i], uoff), u1 = ldUnit<SC>(rin[i], uoff + 8);
+        uint64_t u0[U], u1[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t uoff = (uint32_t)(p0 + stride * u) * 16;
+          u0[u] = valid[u] ? ldUnit<SC>(rin[i], uoff) : ((uint64_t)flag << 32);
+          u1[u] = valid[u] ? ldUnit<SC>(rin[i], uoff + 8) : ((uint64_t)flag << 32);
+        }
         Spinner sp;
-        while ((uint32_t)(u0 >> 32) != flag || (uint32_t)(u1 >> 32) != flag) {
+        for (;;) {
+          uint32_t pend = 0;
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if ((uint32_t)(u0[u] >> 32) != flag || (uint32_t)(u1[u] >> 32) != flag) pend |= 1u << u;
+          if (pend == 0) break;
           if (!sp.tick(c)) { alive = false; break; }
-          u0 = ldUnit<SC>(rin[i], uoff);
-          u1 = ldUnit<SC>(rin[i], uoff + 8);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (pend & (1u << u)) {
+              const uint32_t uoff = (uint32_t)(p0 + stride * u) * 16;
+              u0[u] = ldUnit<SC>(rin[i], uoff);
+              u1[u] = ldUnit<SC>(rin[i], uoff + 8);
+            }
+          }
         }
-        if (have) {
-          acc[0] = redWord<DT, OP>(acc[0], (uint32_t)u0);
-          acc[1] = redWord<DT, OP>(acc[1], (uint32_t)u1);
-        } else {
-          acc[0] = (uint32_t)u0;
-          acc[1] = (uint32_t)u1;
-          have = true;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (have) {
+            acc[u][0] = redWord<DT, OP>(acc[u][0], (uint32_t)u0[u]);
+            acc[u][1] = redWord<DT, OP>(acc[u][1], (uint32_t)u1[u]);
+          } else {
+            acc[u][0] = (uint32_t)u0[u];
+            acc[u][1] = (uint32_t)u1[u];
+          }
         }
+        have = true;
       }
     }
     if (!alive) break;
-    if (writeDst) {
-      if (valid == 8) __builtin_amdgcn_raw_buffer_store_b64(u32x2{acc[0], acc[1]}, bdst, (uint32_t)off, 0, 0);
-      else storePart<E, 2>(a.dst + off, valid, acc);
-    }
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      if (a.smask & (1 << j)) {
-        const uint64_t flag = (uint64_t)(uint32_t)(s[j].step + 1) << 32;
-        stUnit<SC>(sout[j], (uint32_t)p * 16, (uint64_t)acc[0] | flag);
-        stUnit<SC>(sout[j], (uint32_t)p * 16 + 8, (uint64_t)acc[1] | flag);
+    for (int u = 0; u < U; ++u) {
+      if (valid[u] == 0) continue;
+      const uint64_t p = p0 + stride * u;
+      const uint64_t off = p * 8;
+      if (writeDst) {
+        if (valid[u] == 8) __builtin_amdgcn_raw_buffer_store_b64(u32x2{acc[u][0], acc[u][1]}, bdst, (uint32_t)off, 0, 0);
+        else storePart<E, 2>(a.dst + off, valid[u], acc[u]);
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (a.smask & (1 << j)) {
+          const uint64_t flag = (uint64_t)(uint32_t)(s[j].step + 1) << 32;
+          stUnit<SC>(sout[j], (uint32_t)p * 16, (uint64_t)acc[u][0] | flag);
+          stUnit<SC>(sout[j], (uint32_t)p * 16 + 8, (uint64_t)acc[u][1] | flag);
+        }
       }
     }
   }
@@ -556,13 +654,20 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 }
 
 // ------------------------------------------------------------------ LL128 datapath
-// Lane l of a wave handles 16 bytes (word pair l % 8) of line l / 8 of the
-// wave's group of 8 lines; lane 7 of each line carries 8 payload bytes and
-// the 8-byte flag.
+// Lane l of a wave handles 16 bytes (word pair l % 8) of line l / 8 of an
+// 8-line group; lane 7 of each line carries 8 payload bytes and the 8-byte
+// flag.  A pass covers nwaves * LL128_UNROLL groups, wave-major (group
+// wave + nwaves * u), so a short step spreads over the waves and a long one
+// keeps LL128_UNROLL groups in flight per wave.  Every line load of a pass is
+// issued before any flag is checked, and only lines whose flag is still
+// stale are read again.
+
+constexpr int LL128_UNROLL = 4;
 
 template <int SC, int DT, int OP>
 __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   constexpr int E = ElemSize<DT>::value;
+  constexpr int U = LL128_UNROLL;
   if (!waitCredits<SC>(c, s, a.smask)) return false;
   const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL128];
   const uint32_t nlines = (uint32_t)((a.nbytes + LL128_DATA - 1) / LL128_DATA);
@@ -578,85 +683,111 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   const int g = c.lid >> 3, j = c.lid & 7;
   const int plen = (j < 7) ? 16 : 8;
   bool alive = true;
-  for (uint32_t L0 = (uint32_t)c.wave * 8; L0 < nlines; L0 += (uint32_t)c.nwaves * 8) {
-    const uint32_t line = L0 + g;
-    const bool act = line < nlines;
-    const uint64_t payOff = (uint64_t)line * LL128_DATA + 16u * j;
-    const uint32_t loff = line * LL128_LINE + 16u * j;
-    int valid = 0;
-    if (act && payOff < a.nbytes) valid = (int)((a.nbytes - payOff) < (uint64_t)plen ? (a.nbytes - payOff) : plen);
-    uint32_t acc[4] = {0, 0, 0, 0};
-    bool have = false;
-    if (a.src) {
-      if (valid == plen) {
-        // user buffers: full pieces through buffer accesses at any element
-        // alignment, a short piece element by element
-        if (plen == 16) {
-          const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(bsrc, (uint32_t)payOff, 0, LOAD_AUX);
-          acc[0] = v.x;
-          acc[1] = v.y;
-          acc[2] = v.z;
-          acc[3] = v.w;
-        } else {
-          const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)payOff, 0, LOAD_AUX);
-          acc[0] = v.x;
-          acc[1] = v.y;
+  for (uint32_t L0 = 0; L0 < nlines; L0 += (uint32_t)c.nwaves * 8 * U) {
+    uint32_t acc[U][4];
+    uint32_t lineOf[U];
+    int valid[U];
+    bool act[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t line = L0 + 8 * ((uint32_t)c.wave + (uint32_t)c.nwaves * u) + g;
+      lineOf[u] = line;
+      act[u] = line < nlines;
+      const uint64_t payOff = (uint64_t)line * LL128_DATA + 16u * j;
+      valid[u] = 0;
+      if (act[u] && payOff < a.nbytes)
+        valid[u] = (int)((a.nbytes - payOff) < (uint64_t)plen ? (a.nbytes - payOff) : plen);
+      acc[u][0] = acc[u][1] = acc[u][2] = acc[u][3] = 0;
+      if (a.src) {
+        if (valid[u] == plen) {
+          // user buffers: full pieces through buffer accesses at any element
+          // alignment, a short piece element by element
+          if (plen == 16) {
+            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(bsrc, (uint32_t)payOff, 0, LOAD_AUX);
+            acc[u][0] = v.x;
+            acc[u][1] = v.y;
+            acc[u][2] = v.z;
+            acc[u][3] = v.w;
+          } else {
+            const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(bsrc, (uint32_t)payOff, 0, LOAD_AUX);
+            acc[u][0] = v.x;
+            acc[u][1] = v.y;
+          }
+        } else if (valid[u] > 0) {
+          loadPart<E, 4, true>(a.src + payOff, valid[u], acc[u]);
         }
-      } else if (valid > 0) {
-        loadPart<E, 4, true>(a.src + payOff, valid, acc);
       }
-      have = true;
     }
+    bool have = a.src != nullptr;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       if (alive && (a.rmask & (1 << i))) {
         const uint64_t flag = r[i].step + 1;
-        u32x4 v = act ? ldLine16<SC>(rin[i], loff) : u32x4{0, 0, 0, 0};
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          v[u] = act[u] ? ldLine16<SC>(rin[i], lineOf[u] * LL128_LINE + 16u * j) : u32x4{0, 0, 0, 0};
         Spinner sp;
         for (;;) {
-          // lane 7 of each line holds the flag; the whole line is re-read
-          // (one 8-lane load) until the flag is current
-          const int flagOk = (!act || j != 7 || ((((uint64_t)v.w << 32) | v.z) == flag)) ? 1 : 0;
-          const bool lineOk = __shfl(flagOk, c.lid | 7) != 0;
-          if (__all(lineOk)) break;
+          // lane 7 of each line holds the flag; a line is re-read whole (one
+          // 8-lane load) until its flag is current
+          uint32_t pend = 0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int flagOk = (!act[u] || j != 7 || ((((uint64_t)v[u].w << 32) | v[u].z) == flag)) ? 1 : 0;
+            if (__shfl(flagOk, c.lid | 7) == 0) pend |= 1u << u;
+          }
+          if (__all(pend == 0)) break;
           if (__any(!sp.tick(c))) { alive = false; break; }
-          if (!lineOk) v = ldLine16<SC>(rin[i], loff);
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (pend & (1u << u)) v[u] = ldLine16<SC>(rin[i], lineOf[u] * LL128_LINE + 16u * j);
         }
-        const uint32_t pw0 = v.x, pw1 = v.y, pw2 = (j < 7) ? v.z : 0u, pw3 = (j < 7) ? v.w : 0u;
-        if (have) {
-          acc[0] = redWord<DT, OP>(acc[0], pw0);
-          acc[1] = redWord<DT, OP>(acc[1], pw1);
-          acc[2] = redWord<DT, OP>(acc[2], pw2);
-          acc[3] = redWord<DT, OP>(acc[3], pw3);
-        } else {
-          acc[0] = pw0;
-          acc[1] = pw1;
-          acc[2] = pw2;
-          acc[3] = pw3;
-          have = true;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t pw0 = v[u].x, pw1 = v[u].y, pw2 = (j < 7) ? v[u].z : 0u, pw3 = (j < 7) ? v[u].w : 0u;
+          if (have) {
+            acc[u][0] = redWord<DT, OP>(acc[u][0], pw0);
+            acc[u][1] = redWord<DT, OP>(acc[u][1], pw1);
+            acc[u][2] = redWord<DT, OP>(acc[u][2], pw2);
+            acc[u][3] = redWord<DT, OP>(acc[u][3], pw3);
+          } else {
+            acc[u][0] = pw0;
+            acc[u][1] = pw1;
+            acc[u][2] = pw2;
+            acc[u][3] = pw3;
+          }
         }
+        have = true;
       }
     }
     if (!alive) break;
-    if (writeDst && valid > 0) {
-      if (valid == plen) {
-        if (plen == 16) __builtin_amdgcn_raw_buffer_store_b128(u32x4{acc[0], acc[1], acc[2], acc[3]}, bdst, (uint32_t)payOff, 0, 0);
-        else __builtin_amdgcn_raw_buffer_store_b64(u32x2{acc[0], acc[1]}, bdst, (uint32_t)payOff, 0, 0);
-      } else {
-        storePart<E, 4>(a.dst + payOff, valid, acc);
-      }
-    }
-    if (act) {
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        if (a.smask & (1 << q)) {
-          const uint64_t flag = s[q].step + 1;
-          u32x4 w = {acc[0], acc[1], acc[2], acc[3]};
-          if (j == 7) {
-            w.z = (uint32_t)flag;
-            w.w = (uint32_t)(flag >> 32);
+    for (int u = 0; u < U; ++u) {
+      const uint32_t line = lineOf[u];
+      const uint64_t payOff = (uint64_t)line * LL128_DATA + 16u * j;
+      if (writeDst && valid[u] > 0) {
+        if (valid[u] == plen) {
+          if (plen == 16)
+            __builtin_amdgcn_raw_buffer_store_b128(u32x4{acc[u][0], acc[u][1], acc[u][2], acc[u][3]}, bdst, (uint32_t)payOff, 0, 0);
+          else
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{acc[u][0], acc[u][1]}, bdst, (uint32_t)payOff, 0, 0);
+        } else {
+          storePart<E, 4>(a.dst + payOff, valid[u], acc[u]);
+        }
+      }
+      if (act[u]) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (a.smask & (1 << q)) {
+            const uint64_t flag = s[q].step + 1;
+            u32x4 w = {acc[u][0], acc[u][1], acc[u][2], acc[u][3]};
+            if (j == 7) {
+              w.z = (uint32_t)flag;
+              w.w = (uint32_t)(flag >> 32);
+            }
+            stLine16<SC>(sout[q], line * LL128_LINE + 16u * j, w);
           }
-          stLine16<SC>(sout[q], loff, w);
         }
       }
     }
@@ -715,8 +846,8 @@ __device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, C
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    r[i].step = sSteps[i];
-    s[i].step = sSteps[3 + i];
+    r[i].step = uniform64(sSteps[i]);
+    s[i].step = uniform64(sSteps[3 + i]);
   }
   __syncthreads();
 }
@@ -741,9 +872,9 @@ __device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
   const uint64_t full = w.chCount / loopCount, rem = w.chCount - full * loopCount;
   const uint64_t nloops = full + (rem ? 1 : 0);
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
-  const char* sendb = args.send[me];
-  char* recvb = args.recv[me];
-  char* nextRecv = args.recv[nxt];
+  const char* sendb = uniformPtr(args.send[me]);
+  char* recvb = uniformPtr(args.recv[me]);
+  char* nextRecv = uniformPtr(args.recv[nxt]);
   for (uint64_t l = 0; l < nloops; ++l) {
     const uint64_t base = l * loopCount;
     const uint64_t Kl = (l < full) ? K : roundUp(ceilDiv(rem, R), A);
@@ -794,8 +925,8 @@ __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArg
   const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, n = w.count, K = w.chunk;
-  const char* sendb = args.send[me];
-  char* recvb = args.recv[me];
+  const char* sendb = uniformPtr(args.send[me]);
+  char* recvb = uniformPtr(args.recv[me]);
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
     const uint64_t len = umin(K, w.chCount - a0);
     for (int t = 0; t < R; ++t) {
@@ -822,9 +953,9 @@ __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& a
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t n = w.count, K = w.chunk;
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
-  const char* sendb = args.send[me];
-  char* recvb = args.recv[me];
-  char* nextRecv = args.recv[nxt];
+  const char* sendb = uniformPtr(args.send[me]);
+  char* recvb = uniformPtr(args.recv[me]);
+  char* nextRecv = uniformPtr(args.recv[nxt]);
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
     const uint64_t len = umin(K, w.chCount - a0);
     for (int t = 0; t < R; ++t) {
@@ -869,16 +1000,16 @@ __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& a
     const uint64_t off = w.chOffset + a0;
     StepArgs a{};
     a.nbytes = len;
-    a.dst = args.recv[me] + off;
+    a.dst = uniformPtr(args.recv[me]) + off;
     if (pos == 0) {
-      a.src = args.send[me] + off;
+      a.src = uniformPtr(args.send[me]) + off;
       a.smask = 1;
     } else {
       a.rmask = 1;
       a.recvDirect = direct;
       if (pos < R - 1) a.smask = 1;
     }
-    if (direct && a.smask) a.sendDirect[0] = args.recv[nxt] + off;
+    if (direct && a.smask) a.sendDirect[0] = uniformPtr(args.recv[nxt]) + off;
     if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
   }
 }
@@ -898,10 +1029,10 @@ __device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args
     const uint64_t off = (w.chOffset + a0) * E;
     StepArgs a{};
     a.nbytes = len * E;
-    a.src = args.send[me] + off;
+    a.src = uniformPtr(args.send[me]) + off;
     a.rmask = pos > 0 ? 1 : 0;
     a.smask = pos < R - 1 ? 1 : 0;
-    if (pos == R - 1) a.dst = args.recv[me] + off;
+    if (pos == R - 1) a.dst = uniformPtr(args.recv[me]) + off;
     if (!step<PROTO, SC, DT, OP>(c, r, s, a)) return;
   }
 }
@@ -940,8 +1071,8 @@ __device__ void treeAllReduce(const Ctx& c0, const WorkItem& w, const CollArgs& 
   const uint64_t E = w.elemBytes, K = w.chunk;
   const uint64_t nch = ceilDiv(w.chCount, K);
   const uint64_t lag = (up && down) ? NSLOTS - 1 : 0;
-  const char* sendb = args.send[me];
-  char* recvb = args.recv[me];
+  const char* sendb = uniformPtr(args.send[me]);
+  char* recvb = uniformPtr(args.recv[me]);
   for (uint64_t j = 0; j < nch + lag; ++j) {
     if (up && j < nch) {
       const uint64_t a0 = j * K, len = umin(K, w.chCount - a0);
@@ -983,8 +1114,8 @@ __device__ void p2pTransfer(const Ctx& c, const WorkItem& w, const CollArgs& arg
   const uint64_t per = (n + R - 1) / R;
   const uint64_t share = (per + 15) / 16 * 16;
   const uint64_t b0 = umin(n, (uint64_t)c.rank * share), b1 = umin(n, ((uint64_t)c.rank + 1) * share);
-  const char* src = args.send[w.root] + w.chOffset;
-  char* dst = args.recv[w.peer] + w.chOffset;
+  const char* src = uniformPtr(args.send[w.root]) + w.chOffset;
+  char* dst = uniformPtr(args.recv[w.peer]) + w.chOffset;
   for (uint64_t a0 = b0; a0 < b1; a0 += w.chunk) {
     PtrList in, out;
     in.add(src + a0);
@@ -994,7 +1125,9 @@ __device__ void p2pTransfer(const Ctx& c, const WorkItem& w, const CollArgs& arg
 }
 
 template <int PROTO, int SC, int DT, int OP>
-__device__ __noinline__ void runItem(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
+__device__ __noinline__ void runItem(const Ctx& c0, const WorkItem& w0, const CollArgs& args, uint64_t* sSteps) {
+  const Ctx c = uniformCtx(c0);
+  const WorkItem w = uniformItem(w0);
   if constexpr (OP == OP_COPY) {
     if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, SC, DT, OP>(c, w, args, sSteps);
     else if (w.coll == COLL_BROADCAST) ringBroadcast<PROTO, SC, DT, OP>(c, w, args, sSteps);
