@@ -233,7 +233,15 @@ struct Ctx {
   int rank, lane, nranks;
   int tid, nthreads, wave, nwaves, lid;
   int* sAbort;  // LDS flag: set when any wait of this workgroup failed
+  uint32_t slotB;   // FIFO slot bytes of the running item's protocol
 };
+
+// LDS words through LDS pointers: LDS instructions wait only on LDS, where a
+// generic pointer's access would also wait on every outstanding memory access
+// of the wave.
+typedef __attribute__((address_space(3))) uint64_t LdsU64;
+typedef volatile __attribute__((address_space(3))) int LdsFlag;
+__device__ __forceinline__ LdsFlag* abortWord(const Ctx& c) { return (LdsFlag*)c.sAbort; }
 
 // Scalar copies of the workgroup-uniform state a work item runs on (the
 // context, the item's words, read from LDS or through a call): every pointer,
@@ -250,6 +258,7 @@ __device__ __forceinline__ Ctx uniformCtx(const Ctx& c0) {
   c.tid = c0.tid;
   c.lid = c0.lid;
   c.sAbort = uniformPtr(c0.sAbort);
+  c.slotB = uniform(c0.slotB);
   return c;
 }
 __device__ __forceinline__ WorkItem uniformItem(const WorkItem& w0) {
@@ -264,9 +273,9 @@ __device__ __forceinline__ WorkItem uniformItem(const WorkItem& w0) {
 
 struct Conn {
   char* fifo = nullptr;       // this connection's FIFO for the current protocol
-  uint64_t* tail = nullptr;
-  uint64_t* head = nullptr;
+  uint64_t* tail = nullptr;   // counter record; head() is in the same record
   uint64_t step = 0;
+  __device__ __forceinline__ uint64_t* head() const { return tail + CTR_HEAD_U64; }
 };
 
 // Slot (step % NSLOTS) may be overwritten once the receiver has consumed step
@@ -290,6 +299,25 @@ __device__ __forceinline__ bool waitCounter(const Ctx& c, const uint64_t* ctr, u
   }
 }
 
+// Before a step: every send in smask needs its slot's credit (head >=
+// creditTarget(step)) and every receive in rmask its chunk (tail >= step + 1).
+// One lane waits; the barrier hands the outcome to every thread.
+template <int SC>
+__device__ __forceinline__ bool syncConns(const Ctx& c, Conn* r, int rmask, Conn* s, int smask) {
+  if (c.tid == 0) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (ok && (smask & (1 << j))) ok = waitCounter<SC>(c, s[j].head(), creditTarget(s[j].step));
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (ok && (rmask & (1 << i))) ok = waitCounter<SC>(c, r[i].tail, r[i].step + 1);
+    if (!ok) *abortWord(c) = 1;
+  }
+  __syncthreads();
+  return !*abortWord(c);
+}
+
 // Per-lane poll helper for flag-based protocols: counts spins and checks the
 // abort word / timeout now and then.
 struct Spinner {
@@ -297,7 +325,7 @@ struct Spinner {
   uint32_t it = 0;
   __device__ __forceinline__ bool tick(const Ctx& c) {
     if ((++it & 255u) == 0) {
-      if (*(volatile int*)c.sAbort) return false;
+      if (*abortWord(c)) return false;
       if (t0 == 0) t0 = nowTicks();
       if (ldSystem32(c.comm->abortFlag)) { orSystem32(c.comm->errorWord, ERR_ABORT); atomicOr(c.sAbort, 1); return false; }
       if (nowTicks() - t0 > c.comm->timeoutTicks) {
@@ -451,22 +479,11 @@ struct StepArgs {
 
 template <int SC, int DT, int OP>
 __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
-  if (c.tid == 0) {
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if (ok && (a.smask & (1 << j))) ok = waitCounter<SC>(c, s[j].head, creditTarget(s[j].step));
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-      if (ok && (a.rmask & (1 << i))) ok = waitCounter<SC>(c, r[i].tail, r[i].step + 1);
-    if (a.rmask) acquireData<SC>();
-    if (!ok) *c.sAbort = 1;
-  }
-  __syncthreads();
-  if (*(volatile int*)c.sAbort) return false;
+  if (!syncConns<SC>(c, r, a.rmask, s, a.smask)) return false;
+  if (a.rmask) acquireData<SC>();
 
   PtrList in, out;
-  const uint64_t slotB = c.comm->slotBytes[PROTO_SIMPLE];
+  const uint64_t slotB = c.slotB;
   if (a.src) in.add(a.src);
   if (a.recvDirect) {
     if (a.smask) in.add(a.dst);  // forward what the peer stored into our buffer
@@ -491,7 +508,7 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
       if (a.smask & (1 << j)) stCtr<SC>(s[j].tail, s[j].step + 1);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      if (a.rmask & (1 << i)) stCtr<SC>(r[i].head, r[i].step + 1);
+      if (a.rmask & (1 << i)) stCtr<SC>(r[i].head(), r[i].step + 1);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -503,29 +520,22 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 }
 
 // Credit wait shared by LL and LL128: the slot about to be written must have
-// been consumed NSLOTS steps ago.
+// been consumed NSLOTS steps ago.  Receives wait on their lines' flags, not
+// on a counter.
 template <int SC>
 __device__ __forceinline__ bool waitCredits(const Ctx& c, Conn* s, int smask) {
-  if (c.tid == 0) {
-    bool ok = true;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if (ok && (smask & (1 << j))) ok = waitCounter<SC>(c, s[j].head, creditTarget(s[j].step));
-    if (!ok) *c.sAbort = 1;
-  }
-  __syncthreads();
-  return !*(volatile int*)c.sAbort;
+  return syncConns<SC>(c, s, 0, s, smask);
 }
 
 template <int SC>
 __device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, int rmask, int smask) {
   drainVmem();
   __syncthreads();
-  bool ok = !*(volatile int*)c.sAbort;
+  bool ok = !*abortWord(c);
   if (c.tid == 0 && ok) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-      if (rmask & (1 << i)) stCtr<SC>(r[i].head, r[i].step + 1);
+      if (rmask & (1 << i)) stCtr<SC>(r[i].head(), r[i].step + 1);
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       if (smask & (1 << j)) stCtr<SC>(s[j].tail, s[j].step + 1);
@@ -553,7 +563,7 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   constexpr int E = ElemSize<DT>::value;
   constexpr int U = LL_UNROLL;
   if (!waitCredits<SC>(c, s, a.smask)) return false;
-  const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL];
+  const uint32_t slotB = c.slotB;
   const uint64_t npairs = (a.nbytes + 7) / 8;
   __amdgpu_buffer_rsrc_t rin[3], sout[3];
 #pragma unroll
@@ -669,7 +679,7 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
   constexpr int E = ElemSize<DT>::value;
   constexpr int U = LL128_UNROLL;
   if (!waitCredits<SC>(c, s, a.smask)) return false;
-  const uint32_t slotB = (uint32_t)c.comm->slotBytes[PROTO_LL128];
+  const uint32_t slotB = c.slotB;
   const uint32_t nlines = (uint32_t)((a.nbytes + LL128_DATA - 1) / LL128_DATA);
   __amdgpu_buffer_rsrc_t rin[3], sout[3];
 #pragma unroll
@@ -819,27 +829,28 @@ __device__ __forceinline__ char* fifoOf(const Ctx& c, int proto, int receiver, i
 // tail) and all threads pick them up from LDS.
 template <int SC>
 __device__ void setupConns(const Ctx& c, int proto, Conn* r, const int* rkind, Conn* s, const int* speer,
-                           const int* skind, uint64_t* sSteps) {
-  const uint64_t fifoBytes = (uint64_t)NSLOTS * c.comm->slotBytes[proto];
+                           const int* skind, uint64_t* sStepsGeneric) {
+  const uint64_t fifoBytes = (uint64_t)NSLOTS * c.slotB;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     if (rkind[i] >= 0) {
       uint64_t id = connId(c, c.rank, rkind[i]);
       r[i].fifo = fifoOf(c, proto, c.rank, rkind[i], fifoBytes);
       r[i].tail = c.comm->ctr + id * CTR_RECORD_U64;
-      r[i].head = r[i].tail + CTR_HEAD_U64;
     }
     if (speer[i] >= 0) {
       uint64_t id = connId(c, speer[i], skind[i]);
       s[i].fifo = fifoOf(c, proto, speer[i], skind[i], fifoBytes);
       s[i].tail = c.comm->ctr + id * CTR_RECORD_U64;
-      s[i].head = s[i].tail + CTR_HEAD_U64;
     }
   }
+  // a receive end starts at the steps it consumed (head), a send end at the
+  // steps it produced (tail)
+  LdsU64* sSteps = (LdsU64*)sStepsGeneric;
   if (c.tid == 0) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      sSteps[i] = rkind[i] >= 0 ? ldCtr<SC>(r[i].head) : 0;
+      sSteps[i] = rkind[i] >= 0 ? ldCtr<SC>(r[i].head()) : 0;
       sSteps[3 + i] = speer[i] >= 0 ? ldCtr<SC>(s[i].tail) : 0;
     }
   }
@@ -1126,7 +1137,8 @@ __device__ void p2pTransfer(const Ctx& c, const WorkItem& w, const CollArgs& arg
 
 template <int PROTO, int SC, int DT, int OP>
 __device__ __noinline__ void runItem(const Ctx& c0, const WorkItem& w0, const CollArgs& args, uint64_t* sSteps) {
-  const Ctx c = uniformCtx(c0);
+  Ctx c = uniformCtx(c0);
+  c.slotB = uniform((uint32_t)c.comm->slotBytes[PROTO]);
   const WorkItem w = uniformItem(w0);
   if constexpr (OP == OP_COPY) {
     if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, SC, DT, OP>(c, w, args, sSteps);
