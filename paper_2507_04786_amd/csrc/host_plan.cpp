@@ -43,7 +43,8 @@ static uint64_t maxChunkBytes(const Clique* c, int proto) {
 
 // Measured plan table: for each (ranks, collective, log2 of the per-rank
 // size) the fastest (algorithm, protocol, channels) of a sweep over all of
-// them on this chip (fewest channels among plans within 10 % of the best).
+// them on this chip (fewest channels among plans within 10 % of the best
+// below 16 MiB, within 3 % from 16 MiB up).
 struct TuneEntry {
   int nranks, coll, log2, algo, proto, nchannels;
   float us;

@@ -7,8 +7,10 @@ point with HIP events on the launch stream, and writes one JSON line per
 point.  ``--emit`` turns one or more such files into the C++ table the
 planner reads (``csrc/tune_table.inc``): for every (ranks, collective, size
 bucket) the fastest measured plan, preferring fewer channels among plans
-within 10 % of the best: a lane left free serves grouped or concurrent work,
-and a grouped launch runs every channel of a collective as its own item.
+within 10 % of the best below 16 MiB (3 % from 16 MiB up): a lane left free
+serves grouped or concurrent work, and a grouped launch runs every channel
+of a collective as its own item, while a large collective's own time
+dominates whatever it shares the device with.
 
 Usage:
   python paper_2507_04786_amd/tune_sweep.py --nranks 8 --out sweep_r8.jsonl
@@ -30,6 +32,8 @@ CHANNELS = (1, 2, 4, 8, 16, 32)
 LOG2_MIN, LOG2_MAX = 3, 28
 SLOW_MS = 4.0   # a plan slower than this at one size is not tried at larger sizes
 TOLERANCE = 1.10  # plans this close to the fastest count as equal; the fewest channels wins
+TOLERANCE_LARGE = 1.03  # the same from LARGE_LOG2 up
+LARGE_LOG2 = 24
 
 
 def sweep(args):
@@ -124,7 +128,8 @@ def emit(paths, dest):
     for key in sorted({(r["R"], r["coll"], r["log2"]) for r in rows}):
         cands = [r for r in rows if (r["R"], r["coll"], r["log2"]) == key]
         tmin = min(r["ms"] for r in cands)
-        near = [r for r in cands if r["ms"] <= tmin * TOLERANCE]
+        tol = TOLERANCE_LARGE if key[2] >= LARGE_LOG2 else TOLERANCE
+        near = [r for r in cands if r["ms"] <= tmin * tol]
         pick = min(near, key=lambda r: (r["Cplan"], r["ms"]))
         best[key] = pick
     lines = ["// Generated by tune_sweep.py --emit from measured sweeps (fp32, sum, tuner-default",
