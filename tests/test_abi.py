@@ -58,3 +58,17 @@ def test_init_rejects_bad_rank_counts():
             assert e.code in (vccl.vcclInvalidArgument, vccl.vcclUnhandledHipError)
         else:
             raise AssertionError("expected an error")
+
+
+def test_c_client_builds_against_the_header(tmp_path):
+    """include/vccl.h is plain C: a C11 program using the collectives, groups
+    and error strings compiles without warnings and links against the
+    library (it runs in the GPU tests)."""
+    import pytest
+    from tests import c_client_build as cb
+    why = cb.available()
+    if why:
+        pytest.skip(why)
+    out = tmp_path / "c_client"
+    cb.build(str(out))
+    assert out.exists() and os.access(str(out), os.X_OK)
