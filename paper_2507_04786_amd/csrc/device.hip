@@ -527,9 +527,12 @@ __device__ __forceinline__ bool waitCredits(const Ctx& c, Conn* s, int smask) {
   return syncConns<SC>(c, s, 0, s, smask);
 }
 
+// End of an LL / LL128 step.  The lines carry their own flags, so the data
+// stores need not be drained before the counters; the barrier only makes sure
+// every wave has read the received slot (its loads returned: their values
+// were used) before the head store frees it.
 template <int SC>
 __device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, int rmask, int smask) {
-  drainVmem();
   __syncthreads();
   bool ok = !*abortWord(c);
   if (c.tid == 0 && ok) {
@@ -1272,6 +1275,7 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
     if (threadIdx.x < sizeof(CollArgs) / 8) ((uint64_t*)&sArgs)[threadIdx.x] = ((const uint64_t*)as)[threadIdx.x];
     __syncthreads();
     dispatchItem(c, sItem, sArgs, sSteps);
+    drainVmem();  // the item's stores complete before the next item reads counters
     __syncthreads();
     if (*(volatile int*)&sAbort) break;
     if (threadIdx.x == 0 && d.stamps && sItem.doneIndex != 0xFFFFFFFFu)
