@@ -2,6 +2,8 @@
 sampled elements against the oracle's closed-form folds (which the CPU tests
 pin to the step simulation), plus properties that hold at any size.
 
+* the benchmark's headline launch: 8 ranks, fp32 N(0,1), 64 MiB per rank,
+  tuner plan, twice in a row.
 * 8 ranks, fp32 N(0,1), 256 MiB per rank (the largest size of the sweep),
   ring AllReduce under Simple (tuner plan and 1 channel), LL and LL128
   (16 channels): bit-exact samples, all ranks identical, fp64 error bound.
@@ -40,6 +42,38 @@ def _sample(rng, n, k=NSAMP):
 def _dev_at(x, idx):
     t = H.torch()
     return x[t.from_numpy(idx).to(x.device)]
+
+
+def test_headline_launch_64mib_tuner_plan(vccl):
+    """The launch the benchmark times: 8 ranks, fp32 N(0,1) from the same
+    generator, 64 MiB per rank, the tuner's plan, issued twice (the second
+    launch continues the connections' step counters): sampled elements
+    bit-exact against the oracle's fold, all ranks identical, every sample
+    within the fp64 recursive-summation bound."""
+    t = H.torch()
+    R, n = 8, 16 * 1024 * 1024
+    xs = si.rank_inputs(si.WL_RING_AR_SWEEP, R, "float32", n)
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        sends = [H.to_dev(x) for x in xs]
+        recvs = [H.empty_dev(n, "float32") for _ in range(R)]
+        idx = _sample(np.random.default_rng(11), n)
+        for launch in range(2):
+            H.call(vccl, comms, "allreduce", sends, recvs, n, "float32")
+            t.cuda.synchronize()
+            assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+            plan = vccl.vcclCommGetLastPlan(comms[0])
+            print(f"headline launch {launch}: plan {plan}", flush=True)
+            want = folds.ring_allreduce(xs, "sum", "float32", plan["nchannels"], plan["chunkBytes"] // 4, idx=idx)
+            g0 = _dev_at(recvs[0], idx).cpu().numpy()
+            assert np.array_equal(g0.view(np.uint32), want.view(np.uint32)), (launch, plan)
+            for r in range(1, R):
+                assert bool(t.equal(recvs[r], recvs[0])), (launch, r)
+            err = np.abs(g0.astype(np.float64) - defs.fp64_sum([x[idx] for x in xs], "float32"))
+            assert (err <= defs.sum_error_bound([x[idx] for x in xs], "float32") * (1 + 1e-9)).all()
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
 
 
 def test_allreduce_256mib_all_protocols(vccl):
