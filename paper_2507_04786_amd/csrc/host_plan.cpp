@@ -42,13 +42,16 @@ static uint64_t maxChunkBytes(const Clique* c, int proto) {
 }
 
 // Measured plan table: for each (ranks, collective, log2 of the per-rank
-// size) the fastest (algorithm, protocol, channels) of a sweep over all of
-// them on this chip (fewest channels among plans within 10 % of the best
-// below 16 MiB, within 3 % from 16 MiB up).
+// size) the fastest (algorithm, protocol, channels, chunk) of a sweep over
+// all of them on this chip (fewest channels among plans within 10 % of the
+// best below 16 MiB, within 3 % from 16 MiB up).  chunkKiB 0: the chunk
+// formula below.
 struct TuneEntry {
-  int nranks, coll, log2, algo, proto, nchannels;
+  int nranks, coll, log2, algo, proto, nchannels, chunkKiB;
   float us;
 };
+// One table for collectives launched alone and in groups: another plan in a
+// group would change a float reduction's order, and so its bits.
 static const TuneEntry kTuneTable[] = {
 #include "tune_table.inc"
 };
@@ -162,6 +165,8 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   uint64_t chunk;
   if (c->apiTune.chunkBytes) chunk = c->apiTune.chunkBytes;
   else if (c->envTune.chunkBytes) chunk = c->envTune.chunkBytes;
+  else if (te && te->chunkKiB > 0 && te->algo == algo && te->proto == proto)
+    chunk = (uint64_t)te->chunkKiB * 1024;
   else {
     if (proto == PROTO_SIMPLE && algo == ALGO_TREE) {
       // a tree pipelines chunks through 2 log2(R) hops: eight chunks per

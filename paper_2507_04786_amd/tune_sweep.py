@@ -2,11 +2,15 @@
 
 Runs every collective of ``--nranks`` virtual ranks at per-rank sizes
 2^3 .. 2^28 bytes (nccl-tests convention: the larger per-rank buffer) under
-every (algorithm, protocol, channel count) the planner can choose, times each
-point with HIP events on the launch stream, and writes one JSON line per
-point.  ``--emit`` turns one or more such files into the C++ table the
-planner reads (``csrc/tune_table.inc``): for every (ranks, collective, size
-bucket) the fastest measured plan, preferring fewer channels among plans
+every (algorithm, protocol, channel count) the planner can choose, and for
+Simple from 1 MiB up every chunk of CHUNKS_SIMPLE (0: the planner's formula),
+times each point with HIP events on the launch stream, and writes one JSON
+line per point.  ``--emit`` turns one or more such files into the C++ table the
+planner reads (``csrc/tune_table.inc``).  One table serves collectives
+launched alone and in groups: a different plan in a group would change the
+order of a float reduction, and a collective's bits would then depend on its
+grouping.  For every (ranks, collective, size bucket) it holds the fastest
+measured plan, preferring fewer channels among plans
 within 10 % of the best below 16 MiB (3 % from 16 MiB up): a lane left free
 serves grouped or concurrent work, and a grouped launch runs every channel
 of a collective as its own item, while a large collective's own time
@@ -29,6 +33,8 @@ COLLS = ("allreduce", "reducescatter", "allgather", "broadcast", "reduce")
 COLL_CODE = {"allreduce": 0, "broadcast": 1, "reduce": 2, "allgather": 3, "reducescatter": 4}
 PROTOS = ("simple", "ll", "ll128")
 CHANNELS = (1, 2, 4, 8, 16, 32)
+CHUNKS_SIMPLE = (0, 32 << 10, 64 << 10, 256 << 10)
+CHUNK_MIN_LOG2 = 20
 LOG2_MIN, LOG2_MAX = 3, 28
 SLOW_MS = 4.0   # a plan slower than this at one size is not tried at larger sizes
 TOLERANCE = 1.10  # plans this close to the fastest count as equal; the fewest channels wins
@@ -77,12 +83,13 @@ def sweep(args):
                     continue
                 for algo in algos:
                     for proto in PROTOS:
-                        for C in CHANNELS:
-                            key = (algo, proto, C)
+                        chunks = CHUNKS_SIMPLE if (proto == "simple" and lg >= CHUNK_MIN_LOG2) else (0,)
+                        for C, ck in [(C, ck) for C in CHANNELS for ck in chunks]:
+                            key = (algo, proto, C, ck)
                             if key in slow:
                                 continue
                             vccl.vcclCommSetTuning(comms[0], algo=vccl.ALGO_NAMES[algo],
-                                                   proto=vccl.PROTO_NAMES[proto], nchannels=C)
+                                                   proto=vccl.PROTO_NAMES[proto], nchannels=C, chunkBytes=ck)
                             issue(coll, n)
                             torch.cuda.synchronize()
                             plan = vccl.vcclCommGetLastPlan(comms[0])
@@ -104,7 +111,7 @@ def sweep(args):
                             err = vccl.vcclCommGetAsyncError(comms[0])
                             if err != vccl.vcclSuccess:
                                 raise RuntimeError(f"device error at {coll} {S} {key}")
-                            rec = dict(R=R, coll=coll, S=S, log2=lg, algo=algo, proto=proto, C=C,
+                            rec = dict(R=R, coll=coll, S=S, log2=lg, algo=algo, proto=proto, C=C, chunkReq=ck,
                                        Cplan=plan["nchannels"], chunk=plan["chunkBytes"],
                                        T=plan["nthreads"], direct=plan["direct"], ms=round(ms, 5),
                                        wall_ms=round(wall * 1e3, 5), reps=reps)
@@ -120,28 +127,36 @@ def sweep(args):
         out.close()
 
 
-def emit(paths, dest):
-    rows = []
-    for p in paths:
-        rows += [json.loads(line) for line in open(p) if line.strip()]
+def pick_best(rows):
     best = {}
     for key in sorted({(r["R"], r["coll"], r["log2"]) for r in rows}):
         cands = [r for r in rows if (r["R"], r["coll"], r["log2"]) == key]
         tmin = min(r["ms"] for r in cands)
         tol = TOLERANCE_LARGE if key[2] >= LARGE_LOG2 else TOLERANCE
         near = [r for r in cands if r["ms"] <= tmin * tol]
-        pick = min(near, key=lambda r: (r["Cplan"], r["ms"]))
-        best[key] = pick
+        best[key] = min(near, key=lambda r: (r["Cplan"], r["ms"]))
+    return best
+
+
+def write_table(best, dest, paths, what):
     lines = ["// Generated by tune_sweep.py --emit from measured sweeps (fp32, sum, tuner-default",
-             "// chunk and threads); one entry per (ranks, collective, log2 of the per-rank size).",
+             "// threads); one entry per (ranks, collective, log2 of the per-rank size), " + what + ".",
              "// Fields: nranks, coll, log2 bytes, algo (0 ring, 1 tree), proto (0 Simple, 1 LL,",
-             "// 2 LL128), channels, measured microseconds.",
+             "// 2 LL128), channels, chunk KiB (0: the planner's formula), measured microseconds.",
              f"// Sources: {', '.join(os.path.basename(p) for p in paths)}"]
     for (R, coll, lg), r in sorted(best.items(), key=lambda kv: (kv[0][0], COLL_CODE[kv[0][1]], kv[0][2])):
-        lines.append("{%d, %d, %d, %d, %d, %d, %.1f}," % (R, COLL_CODE[coll], lg, 0 if r["algo"] == "ring" else 1,
-                                                        PROTOS.index(r["proto"]), r["Cplan"], r["ms"] * 1e3))
+        lines.append("{%d, %d, %d, %d, %d, %d, %d, %.1f}," % (R, COLL_CODE[coll], lg, 0 if r["algo"] == "ring" else 1,
+                                                            PROTOS.index(r["proto"]), r["Cplan"],
+                                                            r.get("chunkReq", 0) // 1024, r["ms"] * 1e3))
     open(dest, "w").write("\n".join(lines) + "\n")
     print(f"wrote {len(best)} entries to {dest}")
+
+
+def emit(paths, dest):
+    rows = []
+    for p in paths:
+        rows += [json.loads(line) for line in open(p) if line.strip()]
+    write_table(pick_best(rows), dest, paths, "alone or in a group")
 
 
 def main():
