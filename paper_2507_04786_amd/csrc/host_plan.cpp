@@ -42,12 +42,12 @@ static uint64_t maxChunkBytes(const Clique* c, int proto) {
 }
 
 // Measured plan table: for each (ranks, collective, log2 of the per-rank
-// size) the fastest (algorithm, protocol, channels, chunk) of a sweep over
-// all of them on this chip (fewest channels among plans within 10 % of the
-// best below 16 MiB, within 3 % from 16 MiB up).  chunkKiB 0: the chunk
-// formula below.
+// size) the fastest (algorithm, protocol, channels, chunk, threads) of a
+// sweep over all of them on this chip (fewest channels among plans within
+// 10 % of the best below 16 MiB, within 3 % from 16 MiB up).  chunkKiB and
+// nthreads 0: the formulas below.
 struct TuneEntry {
-  int nranks, coll, log2, algo, proto, nchannels, chunkKiB;
+  int nranks, coll, log2, algo, proto, nchannels, chunkKiB, nthreads;
   float us;
 };
 // One table for collectives launched alone and in groups: another plan in a
@@ -147,6 +147,10 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   // --- workgroup size
   long dfltT = (S >= (256u << 10)) ? 512 : 256;
   if (proto == PROTO_SIMPLE) dfltT = 256;
+  // the table's workgroup size, for a collective launched alone (a group runs
+  // every item at the largest size among its plans; the size never changes
+  // a result's bits)
+  if (single && te && te->nthreads > 0 && te->algo == algo && te->proto == proto) dfltT = te->nthreads;
   int nthreads = (int)pickPos(c->apiTune.nthreads, c->envTune.nthreads, dfltT);
   nthreads = std::max(64, std::min(1024, nthreads / 64 * 64));
   // co-residency: every workgroup of the launch must be resident at once

@@ -2,10 +2,11 @@
 
 Runs every collective of ``--nranks`` virtual ranks at per-rank sizes
 2^3 .. 2^28 bytes (nccl-tests convention: the larger per-rank buffer) under
-every (algorithm, protocol, channel count) the planner can choose, and for
-Simple from 1 MiB up every chunk of CHUNKS_SIMPLE (0: the planner's formula),
-times each point with HIP events on the launch stream, and writes one JSON
-line per point.  ``--emit`` turns one or more such files into the C++ table the
+every (algorithm, protocol, channel count) the planner can choose, for
+Simple from 1 MiB up every chunk of CHUNKS_SIMPLE (0: the planner's formula)
+and for LL / LL128 from 64 KiB up every workgroup size of THREADS_FLAG (0:
+the formula), times each point with HIP events on the launch stream, and
+writes one JSON line per point.  ``--emit`` turns one or more such files into the C++ table the
 planner reads (``csrc/tune_table.inc``).  One table serves collectives
 launched alone and in groups: a different plan in a group would change the
 order of a float reduction, and a collective's bits would then depend on its
@@ -35,6 +36,8 @@ PROTOS = ("simple", "ll", "ll128")
 CHANNELS = (1, 2, 4, 8, 16, 32)
 CHUNKS_SIMPLE = (0, 32 << 10, 64 << 10, 256 << 10)
 CHUNK_MIN_LOG2 = 20
+THREADS_FLAG = (0, 256, 1024)  # 0: the formula (512 from 256 KiB, else 256)
+THREADS_MIN_LOG2 = 16
 LOG2_MIN, LOG2_MAX = 3, 28
 SLOW_MS = 4.0   # a plan slower than this at one size is not tried at larger sizes
 TOLERANCE = 1.10  # plans this close to the fastest count as equal; the fewest channels wins
@@ -84,12 +87,14 @@ def sweep(args):
                 for algo in algos:
                     for proto in PROTOS:
                         chunks = CHUNKS_SIMPLE if (proto == "simple" and lg >= CHUNK_MIN_LOG2) else (0,)
-                        for C, ck in [(C, ck) for C in CHANNELS for ck in chunks]:
-                            key = (algo, proto, C, ck)
+                        threads = THREADS_FLAG if (proto != "simple" and lg >= THREADS_MIN_LOG2) else (0,)
+                        for C, ck, th in [(C, ck, th) for C in CHANNELS for ck in chunks for th in threads]:
+                            key = (algo, proto, C, ck, th)
                             if key in slow:
                                 continue
                             vccl.vcclCommSetTuning(comms[0], algo=vccl.ALGO_NAMES[algo],
-                                                   proto=vccl.PROTO_NAMES[proto], nchannels=C, chunkBytes=ck)
+                                                   proto=vccl.PROTO_NAMES[proto], nchannels=C, chunkBytes=ck,
+                                                   nthreads=th)
                             issue(coll, n)
                             torch.cuda.synchronize()
                             plan = vccl.vcclCommGetLastPlan(comms[0])
@@ -111,7 +116,7 @@ def sweep(args):
                             err = vccl.vcclCommGetAsyncError(comms[0])
                             if err != vccl.vcclSuccess:
                                 raise RuntimeError(f"device error at {coll} {S} {key}")
-                            rec = dict(R=R, coll=coll, S=S, log2=lg, algo=algo, proto=proto, C=C, chunkReq=ck,
+                            rec = dict(R=R, coll=coll, S=S, log2=lg, algo=algo, proto=proto, C=C, chunkReq=ck, Treq=th,
                                        Cplan=plan["nchannels"], chunk=plan["chunkBytes"],
                                        T=plan["nthreads"], direct=plan["direct"], ms=round(ms, 5),
                                        wall_ms=round(wall * 1e3, 5), reps=reps)
@@ -127,10 +132,21 @@ def sweep(args):
         out.close()
 
 
+def _plan_key(r):
+    return (r["algo"], r["proto"], r["Cplan"], r.get("chunkReq", 0), r.get("Treq", 0))
+
+
 def pick_best(rows):
+    """Per (ranks, collective, size): every plan's time averaged over the
+    sweep runs that measured it (one run's figure for a plan can be off by
+    20 %), then the fastest, preferring fewer channels within tolerance."""
     best = {}
     for key in sorted({(r["R"], r["coll"], r["log2"]) for r in rows}):
-        cands = [r for r in rows if (r["R"], r["coll"], r["log2"]) == key]
+        runs = {}
+        for r in rows:
+            if (r["R"], r["coll"], r["log2"]) == key:
+                runs.setdefault(_plan_key(r), []).append(r)
+        cands = [dict(rs[0], ms=sum(x["ms"] for x in rs) / len(rs)) for rs in runs.values()]
         tmin = min(r["ms"] for r in cands)
         tol = TOLERANCE_LARGE if key[2] >= LARGE_LOG2 else TOLERANCE
         near = [r for r in cands if r["ms"] <= tmin * tol]
@@ -142,12 +158,13 @@ def write_table(best, dest, paths, what):
     lines = ["// Generated by tune_sweep.py --emit from measured sweeps (fp32, sum, tuner-default",
              "// threads); one entry per (ranks, collective, log2 of the per-rank size), " + what + ".",
              "// Fields: nranks, coll, log2 bytes, algo (0 ring, 1 tree), proto (0 Simple, 1 LL,",
-             "// 2 LL128), channels, chunk KiB (0: the planner's formula), measured microseconds.",
+             "// 2 LL128), channels, chunk KiB (0: the planner's formula), threads (0: the formula;",
+             "// used for a collective launched alone), measured microseconds.",
              f"// Sources: {', '.join(os.path.basename(p) for p in paths)}"]
     for (R, coll, lg), r in sorted(best.items(), key=lambda kv: (kv[0][0], COLL_CODE[kv[0][1]], kv[0][2])):
-        lines.append("{%d, %d, %d, %d, %d, %d, %d, %.1f}," % (R, COLL_CODE[coll], lg, 0 if r["algo"] == "ring" else 1,
-                                                            PROTOS.index(r["proto"]), r["Cplan"],
-                                                            r.get("chunkReq", 0) // 1024, r["ms"] * 1e3))
+        lines.append("{%d, %d, %d, %d, %d, %d, %d, %d, %.1f}," % (
+            R, COLL_CODE[coll], lg, 0 if r["algo"] == "ring" else 1, PROTOS.index(r["proto"]), r["Cplan"],
+            r.get("chunkReq", 0) // 1024, r.get("Treq", 0), r["ms"] * 1e3))
     open(dest, "w").write("\n".join(lines) + "\n")
     print(f"wrote {len(best)} entries to {dest}")
 

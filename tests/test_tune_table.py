@@ -13,7 +13,7 @@ TABLE = os.path.join(ROOT, "paper_2507_04786_amd", "csrc", "tune_table.inc")
 sys.path.insert(0, os.path.join(ROOT, "paper_2507_04786_amd"))
 import tune_sweep as ts  # noqa: E402
 
-ROW = re.compile(r"^\{(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), ([\d.]+)\},$")
+ROW = re.compile(r"^\{(\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), (\d+), ([\d.]+)\},$")
 
 
 def _rows():
@@ -24,9 +24,9 @@ def _rows():
             continue
         m = ROW.match(line)
         assert m, f"malformed table row: {line}"
-        R, coll, lg, algo, proto, C, chunk_kib = (int(x) for x in m.groups()[:7])
+        R, coll, lg, algo, proto, C, chunk_kib, threads = (int(x) for x in m.groups()[:8])
         out.append(dict(R=R, coll=coll, lg=lg, algo=algo, proto=proto, C=C, chunk_kib=chunk_kib,
-                        us=float(m.group(8))))
+                        threads=threads, us=float(m.group(9))))
     return out
 
 
@@ -53,11 +53,14 @@ def test_table_plans_are_legal():
         if r["chunk_kib"]:
             assert r["proto"] == 0 and r["lg"] >= ts.CHUNK_MIN_LOG2, r
             assert r["chunk_kib"] * 1024 in ts.CHUNKS_SIMPLE, r
+        if r["threads"]:
+            assert r["proto"] != 0 and r["lg"] >= ts.THREADS_MIN_LOG2, r
+            assert r["threads"] in ts.THREADS_FLAG, r
         assert r["us"] > 0, r
 
 
-def _rec(lg, C, ms, proto="simple", algo="ring", chunk=0):
-    return dict(R=8, coll="allreduce", S=1 << lg, log2=lg, algo=algo, proto=proto, C=C, chunkReq=chunk,
+def _rec(lg, C, ms, proto="simple", algo="ring", chunk=0, threads=0):
+    return dict(R=8, coll="allreduce", S=1 << lg, log2=lg, algo=algo, proto=proto, C=C, chunkReq=chunk, Treq=threads,
                 Cplan=C, chunk=chunk, T=256, direct=1, ms=ms, wall_ms=ms, reps=3)
 
 
@@ -67,7 +70,7 @@ def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
         # below 16 MiB: 8 channels are 9 % slower than 32 -> within 10 %, taken
         _rec(small, 32, 1.00), _rec(small, 8, 1.09), _rec(small, 4, 1.20),
         # from 16 MiB: 16 channels 5 % slower -> outside 3 %, the fastest wins
-        _rec(large, 32, 1.00, chunk=64 << 10), _rec(large, 16, 1.05), _rec(large, 8, 1.02, proto="ll"),
+        _rec(large, 32, 1.00, chunk=64 << 10), _rec(large, 16, 1.05), _rec(large, 8, 1.02, proto="ll", threads=1024),
     ]
     src = tmp_path / "sweep.jsonl"
     src.write_text("\n".join(json.dumps(r) for r in recs) + "\n")
@@ -75,11 +78,11 @@ def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
     ts.emit([str(src)], str(dest))
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     got = {int(r[2]): r for r in rows}
-    assert got[small][3:7] == ("0", "0", "8", "0")     # ring Simple, 8 channels, formula chunk
-    assert got[large][3:7] == ("0", "1", "8", "0")     # LL at 8 channels is within 3 % and has fewer
+    assert got[small][3:8] == ("0", "0", "8", "0", "0")     # ring Simple, 8 channels, formulas
+    assert got[large][3:8] == ("0", "1", "8", "0", "1024")  # LL at 8 channels: within 3 %, fewer
     # without the LL point the 32-channel plan with its 64 KiB chunk wins
     src.write_text("\n".join(json.dumps(r) for r in recs if r["proto"] == "simple") + "\n")
     ts.emit([str(src)], str(dest))
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     got = {int(r[2]): r for r in rows}
-    assert got[large][3:7] == ("0", "0", "32", "64")
+    assert got[large][3:8] == ("0", "0", "32", "64", "0")
