@@ -154,10 +154,11 @@ def test_tree_allreduce_matrix(vccl, comms_for, proto, dtype, op):
 @pytest.mark.parametrize("R", [4, 8, 16])
 def test_default_plans_match_oracle(vccl, comms_for, R):
     """Whatever the measured tuner picks (ring or tree, any protocol, up to 32
-    channels) at sizes across the 8 B .. 2 MiB range, with ragged counts:
-    every collective against the oracle's folds for the plan it reports."""
+    channels, tabulated chunks and workgroup sizes) at sizes across the
+    8 B .. 4 MiB range, with ragged counts: every collective against the
+    oracle's folds for the plan it reports."""
     comms = comms_for(R)
-    for lg in (3, 6, 10, 13, 16, 17, 18, 20, 21):
+    for lg in (3, 6, 10, 13, 16, 17, 18, 20, 21, 22):
         for coll, dtype in (("allreduce", "float32"), ("allreduce", "bfloat16"), ("reducescatter", "float32"),
                             ("allgather", "float32"), ("broadcast", "bfloat16"), ("reduce", "float32")):
             E = H.ELEM[dtype]
