@@ -243,7 +243,8 @@ double estimateCost(const Clique* c, const WorkItem& w) {
   const int R = c->nranks;
   const double bytes = (double)w.chCount * w.unitBytes;
   const double fifo = w.proto == PROTO_SIMPLE ? 1.0 : (w.proto == PROTO_LL ? 2.0 : 16.0 / 15.0);
-  const double lat = w.proto == PROTO_SIMPLE ? 3.0 : 1.0;
+  // measured per-step cost of a ring step (µs) per protocol
+  const double lat = w.proto == PROTO_SIMPLE ? 1.4 : (w.proto == PROTO_LL ? 0.7 : 0.8);
   double steps, traffic;
   if (w.coll == COLL_ALLREDUCE) {
     steps = w.algo == ALGO_TREE ? 2.0 * std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes))
@@ -260,7 +261,9 @@ double estimateCost(const Clique* c, const WorkItem& w) {
     steps = std::ceil(bytes / std::max<double>(1.0, (double)w.chunk * w.unitBytes)) + R;
     traffic = (R + 1.0 + 2.0 * fifo * (R - 1)) * bytes;
   }
-  const double laneBW = 40e3;  // bytes per us a lane moves, all ranks together (order of magnitude)
+  // bytes per µs one lane moves, all its ranks together, while every lane is
+  // busy: about 6 TB/s of traffic shared by 32 lanes
+  const double laneBW = 180e3;
   return steps * lat + traffic / laneBW;
 }
 
