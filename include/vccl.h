@@ -173,10 +173,15 @@ vcclResult_t vcclGroupEnd(void);
 /* ---------------------------------------------------------------- tuning
  * Section III-D and Section II-C: the algorithm and protocol are chosen per
  * call (user setting, else a tuning model), then the channel count.  The
- * library's tuner does the same; these calls and the environment variables
+ * library's tuner takes algorithm, protocol, channels, chunk (Simple) and
+ * workgroup size (LL / LL128, for a collective launched alone) from a table
+ * measured on this device for 4, 8 and 16 ranks and power-of-two sizes,
+ * using the nearest entry.  These calls and the environment variables
  * VCCL_ALGO, VCCL_PROTO (simple|ll|ll128), VCCL_NCHANNELS, VCCL_CHUNK_BYTES,
  * VCCL_NTHREADS, VCCL_DIRECT override it for the whole communicator set.
- * A negative / zero field means "tuner decides". */
+ * A negative / zero field means "tuner decides".  A grouped collective gets
+ * the same plan as the same call launched alone, so its result has the same
+ * bits; only the workgroup size of a group is the largest among its plans. */
 typedef struct {
   int algo;           /* vcclAlgo_t */
   int proto;          /* vcclProto_t */
