@@ -393,7 +393,7 @@ def main():
                          "then `steps` AllReduces of the workload; prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (virtual ranks live on one device); "
+        print(f"bench.py: vccl runs all its virtual ranks on one GPU; "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
