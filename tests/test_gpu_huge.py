@@ -1,0 +1,150 @@
+"""Buffers beyond 4 GiB per rank: 64-bit counts and offsets on every path.
+
+Inputs are a closed-form hash of (rank, index), generated on the device in
+slices, so the expected value at any index is computed on the host from the
+index alone: int32 sums are exact in any order (they wrap mod 2^32), so
+every sampled element of AllReduce and ReduceScatter must equal the sum of
+the hashes, AllGather and Send/Recv must move them unchanged.  Samples
+include the elements around every 4 GiB and 2 GiB byte boundary and the
+tail."""
+import numpy as np
+import pytest
+
+from tests import gpu_harness as H
+
+pytestmark = pytest.mark.gpu
+
+A, B = 2654435761, 40503
+SLICE = 1 << 26
+
+
+def f_host(r, i):
+    v = (np.asarray(i, dtype=np.uint64) * np.uint64(A) + np.uint64(r * B)) & np.uint64(0xFFFFFFFF)
+    return v.astype(np.uint32).view(np.int32)
+
+
+def fill_dev(t, buf, r, base=0):
+    """buf[j] = f(r, base + j), computed on the device slice by slice."""
+    n = buf.numel()
+    for s in range(0, n, SLICE):
+        e = min(n, s + SLICE)
+        idx = t.arange(base + s, base + e, dtype=t.int64, device=buf.device)
+        v = (idx * A + r * B) & 0xFFFFFFFF
+        buf[s:e] = t.where(v >= 1 << 31, v - (1 << 32), v).to(t.int32)
+
+
+def samples(n, k=20000, seed=3):
+    rng = np.random.default_rng(seed)
+    edges = []
+    for b in (1 << 29, 1 << 30, 3 << 29, 1 << 31):  # element indices at 2, 4, 6, 8 GiB of int32
+        if b < n:
+            edges += [b - 2, b - 1, b, b + 1]
+    idx = np.concatenate([rng.integers(0, n, k), np.arange(min(n, 64)), np.arange(max(0, n - 64), n), edges])
+    return np.unique(idx[(idx >= 0) & (idx < n)])
+
+
+def at(t, buf, idx):
+    return buf[t.from_numpy(idx.astype(np.int64)).to(buf.device)].cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def vccl():
+    import paper_2507_04786_amd as v
+    return v
+
+
+def test_allreduce_over_4gib_per_rank(vccl):
+    t = H.torch()
+    R, n = 4, (9 << 30) // 8  # 4.5 GiB of int32 per rank
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        bufs = [t.empty(n, dtype=t.int32, device="cuda") for _ in range(2 * R)]
+        sends, recvs = bufs[:R], bufs[R:]
+        for r in range(R):
+            fill_dev(t, sends[r], r)
+        idx = samples(n)
+        want = sum(f_host(r, idx).astype(np.int64) for r in range(R))
+        want = (want & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+        for proto in ("auto", "ll"):
+            if proto == "auto":
+                H.untune(vccl, comms)
+            else:
+                H.tune(vccl, comms, "ring", proto, nchannels=32)
+            try:
+                print(f"allreduce 4.5 GiB per rank, {proto}", flush=True)
+                H.call(vccl, comms, "allreduce", sends, recvs, n, "int32")
+                t.cuda.synchronize()
+                assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+            finally:
+                H.untune(vccl, comms)
+            for r in range(R):
+                assert np.array_equal(at(t, recvs[r], idx), want), (proto, r)
+        del bufs, sends, recvs
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+        t.cuda.empty_cache()
+
+
+def test_allgather_and_reducescatter_over_4gib(vccl):
+    t = H.torch()
+    R, n = 4, 300 * 1000 * 1000  # blocks of 1.2 GB: 4.8 GB gathered / scattered per rank
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        small = [t.empty(n, dtype=t.int32, device="cuda") for _ in range(R)]
+        big = [t.empty(R * n, dtype=t.int32, device="cuda") for _ in range(R)]
+        # AllGather: rank q contributes f(q, i); everyone ends with all blocks
+        for q in range(R):
+            fill_dev(t, small[q], q)
+        print("allgather 4.8 GB per rank", flush=True)
+        H.call(vccl, comms, "allgather", small, big, n, "int32")
+        t.cuda.synchronize()
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+        idx = samples(R * n)
+        want = f_host(0, idx % n)
+        for q in range(1, R):
+            sel = idx // n == q
+            want[sel] = f_host(q, idx[sel] % n)
+        for r in range(R):
+            assert np.array_equal(at(t, big[r], idx), want), ("allgather", r)
+        # ReduceScatter: rank q's input is f(q, j) over R n elements
+        for q in range(R):
+            fill_dev(t, big[q], q)
+        print("reducescatter 4.8 GB per rank", flush=True)
+        H.call(vccl, comms, "reducescatter", big, small, n, "int32")
+        t.cuda.synchronize()
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+        idx = samples(n)
+        for r in range(R):
+            want = sum(f_host(q, r * n + idx).astype(np.int64) for q in range(R))
+            want = (want & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+            assert np.array_equal(at(t, small[r], idx), want), ("reducescatter", r)
+        del small, big
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+        t.cuda.empty_cache()
+
+
+def test_sendrecv_over_4gib(vccl):
+    t = H.torch()
+    R, n = 2, (9 << 30) // 8
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        src = t.empty(n, dtype=t.int32, device="cuda")
+        dst = t.empty(n, dtype=t.int32, device="cuda")
+        fill_dev(t, src, 5)
+        print("send/recv 4.5 GiB", flush=True)
+        vccl.vcclGroupStart()
+        vccl.vcclSend(src, n, vccl.vcclInt32, 1, comms[0])
+        vccl.vcclRecv(dst, n, vccl.vcclInt32, 0, comms[1])
+        vccl.vcclGroupEnd()
+        t.cuda.synchronize()
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+        idx = samples(n)
+        assert np.array_equal(at(t, dst, idx), f_host(5, idx))
+        del src, dst
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+        t.cuda.empty_cache()
