@@ -271,7 +271,12 @@ typedef struct {
  * receive buffers plus the FIFOs of the lanes they occupy); lanes: concurrent
  * lanes of the persistent kernel (each lane = one workgroup per rank). */
 vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, vcclServer_t* server);
-/* Non-blocking: queues the request; *id receives its identifier. */
+/* Non-blocking: queues the request; *id receives its identifier.  Errors,
+ * before anything is queued: vcclInvalidArgument for an unknown collective,
+ * datatype or op, a root outside 0..nranks-1 (Broadcast, Reduce), a zero
+ * count, a missing or element-misaligned buffer that the collective uses,
+ * or a request whose buffers and FIFOs exceed the budget (it could never be
+ * admitted). */
 vcclResult_t vcclServeSubmit(vcclServer_t server, const vcclRequest_t* req, uint64_t* id);
 /* Makes progress (admits queued requests, retires finished ones) and
  * reports whether `id` has completed; t_done_ns receives the host

@@ -190,3 +190,85 @@ def test_dead_rank_fails_requests_in_bounded_time(vccl):
     finally:
         for c in comms:
             vccl.vcclCommDestroy(c)
+
+
+def test_every_collective_in_place_max_and_errors(vccl):
+    """Broadcast and Reduce (roots at both ends), max, and in-place requests
+    through the server give the per-call bits; int32 results equal their
+    definitions.  Submissions the server can never run fail at once with
+    InvalidArgument: a zero count, more bytes than the budget."""
+    t = H.torch()
+    Rs = 4
+    comms = vccl.vcclCommInitAll(Rs)
+    try:
+        specs = [("broadcast", "bfloat16", "sum", 30011, 0), ("broadcast", "int32", "sum", 4099, Rs - 1),
+                 ("reduce", "int32", "max", 70001, 3), ("reduce", "float32", "sum", 5000, 0),
+                 ("allreduce", "bfloat16", "max", 12345, 0), ("allreduce", "int32", "sum", 65537, 0),
+                 ("reducescatter", "int32", "max", 3001, 0), ("allgather", "float32", "sum", 777, 0)]
+        data = []
+        for k, (coll, dtype, op, n, root) in enumerate(specs):
+            kw = dict(lo=-2**20, hi=2**20) if dtype == "int32" else {}
+            xs = si.rank_inputs(si.WL_SERVING, Rs, dtype, H.send_len(coll, n, Rs), extra=777000 + k, **kw)
+            data.append(xs)
+
+        def run(served, in_place):
+            outs = []
+            srv = vccl.vcclServeCreate(comms, 1 << 30, 8) if served else None
+            try:
+                for (coll, dtype, op, n, root), xs in zip(specs, data):
+                    sends = [H.to_dev(x) for x in xs]
+                    if in_place and coll == "allreduce":
+                        recvs = sends
+                    else:
+                        recvs = [H.empty_dev(H.recv_len(coll, n, Rs), dtype) for _ in range(Rs)]
+                    t.cuda.synchronize()
+                    if served:
+                        rid = vccl.vcclServeSubmit(srv, CODES[coll], vccl.DTYPE_NAMES[dtype], vccl.OP_NAMES[op],
+                                                   root, n, sends, recvs)
+                        _wait(vccl, srv, [rid])
+                    else:
+                        H.call(vccl, comms, coll, sends, recvs, n, dtype, op, root)
+                    t.cuda.current_stream().synchronize()
+                    outs.append([H.from_dev(r, dtype).copy() for r in recvs])
+                if served:
+                    # requests the server can never run fail at submission,
+                    # before any device work; the buffers hold the full count
+                    # either way (in place, 4 x 2 GiB), so a wrong admission
+                    # could not touch memory outside them
+                    big = [t.zeros(1 << 29, dtype=t.int32, device="cuda") for _ in range(Rs)]
+                    t.cuda.synchronize()
+                    for cnt in (0, 1 << 29):  # zero count; 8 GiB in flight against a 1 GiB budget
+                        with pytest.raises(vccl.VcclError) as e:
+                            vccl.vcclServeSubmit(srv, CODES["allreduce"], vccl.vcclInt32, vccl.vcclSum, 0, cnt,
+                                                 big, big)
+                        assert e.value.code == vccl.vcclInvalidArgument, cnt
+                    del big
+            finally:
+                if served:
+                    vccl.vcclServeDestroy(srv)
+            return outs
+
+        for in_place in (False, True):
+            per_call = run(False, in_place)
+            served = run(True, in_place)
+            for k, (coll, dtype, op, n, root) in enumerate(specs):
+                ranks = [root] if coll == "reduce" else range(Rs)
+                for r in ranks:
+                    assert np.array_equal(served[k][r].view(np.uint8), per_call[k][r].view(np.uint8)), \
+                        (k, coll, dtype, op, in_place, r)
+                if dtype == "int32":
+                    xs = data[k]
+                    if coll == "broadcast":
+                        want = [xs[root]] * Rs
+                    elif coll == "reduce":
+                        want = {root: defs.allreduce(xs, op, "int32")[0]}
+                    elif coll == "allreduce":
+                        want = defs.allreduce(xs, op, "int32")
+                    else:
+                        want = defs.reducescatter(xs, op, "int32")
+                    for r in ranks:
+                        assert np.array_equal(served[k][r], want[r]), (k, coll, op, r)
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
