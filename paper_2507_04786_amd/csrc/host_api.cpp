@@ -68,7 +68,7 @@ vcclResult_t launchPrepared(Clique* c, LaunchDesc& d, int grid, int block, const
 
 }  // namespace
 
-vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool grouped) {
+vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
   vcclResult_t st = asyncStatus(c);
   if (st != vcclSuccess) return st;
   if (c->serving) return vcclInvalidUsage;  // the serving kernel owns the lanes
@@ -222,7 +222,6 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn, bool group
   info.grid = grid;
   info.scope = plans[0].scope;
   info.treeRanksPerNode = c->ranksPerNode;
-  (void)grouped;
   return vcclSuccess;
 }
 
@@ -366,7 +365,7 @@ static vcclResult_t enqueueCall(vcclComm_t comm, const Call& call) {
     return vcclSuccess;
   }
   std::vector<Coll> one{coll};
-  return launchColls(c, one, false);
+  return launchColls(c, one);
 }
 
 // Send / Recv (Section II-A): the k-th send from rank a to rank b pairs with
@@ -414,7 +413,7 @@ static vcclResult_t enqueueP2p(vcclComm_t comm, bool isSend, void* buf, size_t c
     return vcclSuccess;
   }
   std::vector<Coll> one{coll};
-  return launchColls(c, one, false);
+  return launchColls(c, one);
 }
 
 vcclResult_t vcclSend(const void* sendbuff, size_t count, vcclDataType_t datatype, int peer, vcclComm_t comm,
@@ -488,7 +487,7 @@ vcclResult_t vcclGroupEnd(void) {
     std::vector<Coll> mine;
     for (auto& pc : colls)
       if (pc.first == c) mine.push_back(pc.second);
-    vcclResult_t r = launchColls(c, mine, true);
+    vcclResult_t r = launchColls(c, mine);
     if (r != vcclSuccess && result == vcclSuccess) result = r;
   }
   return result;

@@ -140,7 +140,7 @@ void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t arg
 double estimateCost(const Clique* c, const WorkItem& w);
 
 // host_api.cpp
-vcclResult_t launchColls(Clique* c, const std::vector<Coll>& colls, bool grouped);
+vcclResult_t launchColls(Clique* c, const std::vector<Coll>& colls);
 
 // env helpers
 std::string envStr(const char* name);
