@@ -33,7 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 COLLS = ("allreduce", "reducescatter", "allgather", "broadcast", "reduce")
 COLL_CODE = {"allreduce": 0, "broadcast": 1, "reduce": 2, "allgather": 3, "reducescatter": 4}
 PROTOS = ("simple", "ll", "ll128")
-CHANNELS = (1, 2, 4, 8, 16, 32)
+CHANNELS = (1, 2, 4, 8, 16, 32, 64)  # 64 where the communicator's lane limit allows it
 CHUNKS_SIMPLE = (0, 32 << 10, 64 << 10, 256 << 10)
 CHUNK_MIN_LOG2 = 20
 THREADS_FLAG = (0, 256, 1024)  # 0: the formula (512 from 256 KiB, else 256)
@@ -92,9 +92,12 @@ def sweep(args):
                             key = (algo, proto, C, ck, th)
                             if key in slow:
                                 continue
-                            vccl.vcclCommSetTuning(comms[0], algo=vccl.ALGO_NAMES[algo],
-                                                   proto=vccl.PROTO_NAMES[proto], nchannels=C, chunkBytes=ck,
-                                                   nthreads=th)
+                            try:
+                                vccl.vcclCommSetTuning(comms[0], algo=vccl.ALGO_NAMES[algo],
+                                                       proto=vccl.PROTO_NAMES[proto], nchannels=C, chunkBytes=ck,
+                                                       nthreads=th)
+                            except vccl.VcclError:
+                                continue  # more channels than this rank count's lane limit
                             issue(coll, n)
                             torch.cuda.synchronize()
                             plan = vccl.vcclCommGetLastPlan(comms[0])
