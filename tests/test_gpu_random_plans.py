@@ -6,7 +6,8 @@ size and a ragged count, runs it on the device with that tuning, and
 compares every rank's output bit for bit with the oracle run on the plan the
 library reports (channels and chunk after its clamps).  The combinations go
 beyond the fixed matrices: odd rank counts with trees and chains, 64- and
-1024-thread workgroups, tiny and slot-sized chunks, every channel count."""
+1024-thread workgroups, tiny and slot-sized chunks, every channel count up
+to the communicator's lane limit (64 for up to 4 ranks)."""
 import numpy as np
 import pytest
 
@@ -32,7 +33,7 @@ def cases(seed=2507, count=NCASES):
         dtype, op = DTYPE_OPS[int(rng.integers(len(DTYPE_OPS)))]
         proto = ("simple", "ll", "ll128")[int(rng.integers(3))]
         algo = "tree" if coll == "allreduce" and rng.random() < 0.4 else "ring"
-        C = int(rng.integers(1, 33))
+        C = int(rng.integers(1, 65))  # clamped to the lane limit when run
         T = int(rng.choice([64, 128, 256, 512, 1024]))
         chunk = int(rng.choice([0, 256, 1024, 4096, 16384, 65536, 131072, 262144]))
         E = ELEM[dtype]
@@ -50,11 +51,18 @@ def vccl():
     return v
 
 
+def lane_limit(ncus, R):
+    """The library's default: a workgroup per CU, in eights, 32 to 64 lanes."""
+    return max(32, min(64, (ncus // R) // 8 * 8))
+
+
 def test_random_plans_match_oracle(vccl):
     t = H.torch()
+    ncus = t.cuda.get_device_properties(0).multi_processor_count
     comm_sets = {}
     try:
         for (i, R, coll, dtype, op, proto, algo, C, T, chunk, n, root) in cases():
+            C = min(C, lane_limit(ncus, R))
             print(f"case {i}: R={R} {coll} {dtype} {op} {proto} {algo} C={C} T={T} chunk={chunk} n={n} "
                   f"root={root}", flush=True)
             if R not in comm_sets:
