@@ -170,6 +170,10 @@ vcclResult_t vcclRecv(void* recvbuff, size_t count, vcclDataType_t datatype, int
 vcclResult_t vcclGroupStart(void);
 vcclResult_t vcclGroupEnd(void);
 
+/* Stream capture: collective calls must not be captured into a HIP graph.
+ * Each launch's workgroups claim their roles relative to a base the host
+ * advances per launch, which a replay would repeat. */
+
 /* ---------------------------------------------------------------- tuning
  * Section III-D and Section II-C: the algorithm and protocol are chosen per
  * call (user setting, else a tuning model), then the channel count.  The
