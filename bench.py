@@ -10,6 +10,9 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
               duration (HIP events on the launch stream over the timed
               region) against the 8 TB/s HBM3E peak
   protocols   the same AllReduce forced to each protocol (busBW, HBM fraction)
+  sizes       the AllReduce at 8 B .. 16 MiB per rank, tuner plan and each
+              protocol forced: us per call (issued from Python), busBW, HBM
+              fraction
   collectives_r16  every collective (and the tree AllReduce) at 16 ranks, bf16,
               64 MiB per rank: busBW and HBM fraction
   alltoall    grouped Send/Recv between all 8 x 8 rank pairs, 64 MiB per rank
@@ -253,6 +256,47 @@ def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):
             "lanes": plan["nlanes"], "items": plan["nitems"], "sampled_blocks_equal": ok}
 
 
+def sizes_leg(vccl, torch, comms, sends, recvs, stream):
+    """The same AllReduce at sizes from 8 B to 16 MiB per rank under the
+    tuner's plan and under each protocol forced (ring): microseconds per call,
+    issued from Python one call per rank (below about 1 MiB the host's issue
+    time, about 13 us a call, dominates), busBW and the HBM fraction of the
+    plan's algorithmic bytes."""
+    R = len(comms)
+    out = {}
+    for S in (8, 64 << 10, 1 << 20, 16 << 20):
+        n = S // 4
+        row = {}
+        for name, algo, proto in (("tuned", -1, -1), ("simple", vccl.vcclAlgoRing, vccl.vcclProtoSimple),
+                                  ("ll", vccl.vcclAlgoRing, vccl.vcclProtoLL),
+                                  ("ll128", vccl.vcclAlgoRing, vccl.vcclProtoLL128)):
+            vccl.vcclCommSetTuning(comms[0], algo=algo, proto=proto)
+
+            def issue():
+                for r in range(R):
+                    vccl.vcclAllReduce(sends[r], recvs[r], n, vccl.vcclFloat32, vccl.vcclSum, comms[r], stream)
+
+            for _ in range(3):
+                issue()
+            torch.cuda.synchronize()
+            reps = 50 if S <= (1 << 20) else 10
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                issue()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / reps / 1e3
+            p = vccl.vcclCommGetLastPlan(comms[0])
+            row[name] = {"us_per_call": round(t * 1e6, 2), "busbw_gbs": round(S / t / 1e9 * 2 * (R - 1) / R, 3),
+                         "hbm_frac": round(alg_bytes_per_launch(p, R, S) / t / 1e9 / HBM_PEAK_GBS, 4),
+                         "algo": ["ring", "tree"][p["algo"]], "proto": ["simple", "ll", "ll128"][p["proto"]],
+                         "nchannels": p["nchannels"]}
+        out[str(S)] = row
+    vccl.vcclCommSetTuning(comms[0])
+    return out
+
+
 def grouped_leg(vccl, torch, si, comms, stream, reps=10):
     """64 collectives issued in one group against 64 separate launches
     (device time between events on the launch stream, and host wall time)."""
@@ -463,6 +507,7 @@ def main():
     traffic = load_traffic(key)
 
     protos = {}
+    sizes = None
     if not args.no_protocols:
         for name, code in (("simple", vccl.vcclProtoSimple), ("ll", vccl.vcclProtoLL), ("ll128", vccl.vcclProtoLL128)):
             vccl.vcclCommSetTuning(comms[0], algo=vccl.vcclAlgoRing, proto=code)
@@ -474,6 +519,7 @@ def main():
                             "ms": round(e * 1e3, 4), "nchannels": p["nchannels"], "chunk_bytes": p["chunkBytes"],
                             "direct": p["direct"]}
         vccl.vcclCommSetTuning(comms[0])
+        sizes = sizes_leg(vccl, torch, comms, sends, recvs, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -541,6 +587,7 @@ def main():
                      "kernel": "vccl::collKernel", "alg_bytes_per_launch": abytes,
                      "avg_launch_ms": round(ev_step * 1e3, 4)},
         "protocols": protos,
+        "sizes": sizes,
         "collectives_r16": colls16,
         "alltoall": a2a,
         "grouped": grouped,
