@@ -6,23 +6,28 @@
 // HBM under one of three protocols (Section III):
 //
 //  * Simple: a slot holds a whole chunk.  The sender waits for a free slot
-//    (head counter), stores the chunk with device-scope coherent stores,
-//    drains them (every wave waits for its stores, then a barrier) and
-//    publishes the tail counter; the receiver waits on tail, reads the slot
-//    with device-scope coherent loads and returns the slot through head.
+//    (head counter), stores the chunk, drains the stores (every wave waits
+//    for its stores, then a barrier) and publishes the tail counter; the
+//    receiver waits on tail, reads the slot and returns it through head.
 //    The receiver waits for the full chunk.
 //  * LL: every 8-byte unit carries 4 bytes of data and a 4-byte flag and is
-//    written and read by one 64-bit device-scope atomic access, so no fence
-//    is needed; the receiver polls each unit's flag.
+//    written by one 64-bit store and read by one 64-bit load, so no fence is
+//    needed; the receiver polls each unit's flag.  A lane handles four pairs
+//    of units per pass and issues all their loads before it polls.
 //  * LL128: every 128-byte line carries 120 bytes of data and an 8-byte flag
 //    and is written by one 16-byte store per lane across 8 lanes (one store
 //    instruction) and read back the same way; the receiver checks the flag
-//    word and re-reads the whole line until it is current.  This relies on
-//    128-byte lines not being torn (see the tear probe below).
+//    word and re-reads the whole line until it is current.  A wave handles
+//    four 8-line groups per pass.  This relies on 128-byte lines not being
+//    torn (see the tear probe below).
+// Loads are device-scope coherent; stores follow the work item's scope (see
+// the memory policy below).
 //
 // Section V-D's mapping is kept where it holds on CDNA: a channel is a
 // workgroup per rank, wave 0 stages the work descriptor in LDS, all waves of
 // the workgroup move 16-byte vectors in an unrolled, wave-uniform loop.
+// Values uniform over the workgroup (the context, the item, stream bases)
+// are read once into scalar registers.
 // "Direct" variants (Section IV-A, P2P_DIRECT) write straight into the peer's
 // receive buffer instead of its FIFO while keeping the head/tail protocol.
 #include <hip/hip_runtime.h>
