@@ -100,6 +100,9 @@ vcclResult_t vcclCommAbort(vcclComm_t comm);
  * after a timeout or an abort).  Does not synchronise. */
 vcclResult_t vcclCommGetAsyncError(vcclComm_t comm, vcclResult_t* asyncError);
 
+/* Section II-A: *count receives the number of ranks of comm's set, *rank the
+ * rank comm stands for (0 .. nranks-1).  vcclInvalidArgument for an unknown
+ * or destroyed handle or a null output. */
 vcclResult_t vcclCommCount(vcclComm_t comm, int* count);
 vcclResult_t vcclCommUserRank(vcclComm_t comm, int* rank);
 
@@ -218,7 +221,10 @@ vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int
 
 /* ---------------------------------------------------------------- failure handling
  * Every wait on the device is bounded: after `timeout_us` microseconds without
- * progress the waiting workgroup records vcclRemoteError and exits. */
+ * progress the waiting workgroup records vcclRemoteError and exits.  Applies
+ * to the whole set from its next launch; the default is VCCL_TIMEOUT_US, else
+ * 5 s.  Synchronises the device.  vcclInvalidArgument for an unknown handle
+ * or a zero timeout. */
 vcclResult_t vcclCommSetTimeout(vcclComm_t comm, uint64_t timeout_us);
 
 /* Test hook: the workgroups of every rank whose bit is set in `mask` skip all
