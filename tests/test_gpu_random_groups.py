@@ -80,10 +80,14 @@ def vccl():
 def test_random_groups_equal_per_call_and_definitions(vccl):
     comm_sets = {}
     try:
-        for (i, R, batch, pairs) in cases():
+        # one communicator set alive at a time, cases grouped by rank count
+        for (i, R, batch, pairs) in sorted(cases(), key=lambda c: (c[1], c[0])):
             print(f"case {i}: R={R} batch={batch} pairs={len(pairs)}", flush=True)
             if R not in comm_sets:
-                comm_sets[R] = vccl.vcclCommInitAll(R)
+                for comms in comm_sets.values():
+                    for c in comms:
+                        vccl.vcclCommDestroy(c)
+                comm_sets = {R: vccl.vcclCommInitAll(R)}
             comms = comm_sets[R]
             inputs = [_inputs(i, k, R, c, d, n) for k, (c, d, n, _) in enumerate(batch)]
             per_call, p1 = _issue(vccl, comms, batch, inputs, pairs, grouped=False)
