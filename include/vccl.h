@@ -80,8 +80,10 @@ vcclResult_t vcclGetVersion(int* version); /* major*100 + minor */
  * current HIP device, otherwise devlist[0] names it and every other entry
  * must name the same device.  Allocates the FIFOs and counters of every
  * (channel, rank, connection) and builds the ring and the double binary tree
- * (Section II-C).  comms[] (caller-owned array of nranks handles) receives one
- * handle per rank.  Errors: vcclInvalidArgument for a bad count or device,
+ * (Section II-C).  The set's lane limit (most channels a collective can use)
+ * is the environment's VCCL_MAX_CHANNELS, else CUs / nranks rounded down to a
+ * multiple of 8 and held to 32..64.  comms[] (caller-owned array of nranks
+ * handles) receives one handle per rank.  Errors: vcclInvalidArgument for a bad count or device,
  * vcclUnhandledHipError if device memory cannot be obtained. */
 vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist);
 
@@ -198,6 +200,13 @@ typedef struct {
   int direct;         /* 1: P2P_DIRECT-style copies into peer buffers (Simple only) */
 } vcclTuning_t;
 
+/* Copies *tuning (caller-owned, read during the call only).  Applies to every
+ * later call of the set.  vcclInvalidArgument, with nothing changed, for an
+ * unknown handle, a null tuning, an algorithm or protocol out of range,
+ * nchannels above the set's lane limit, an illegal nthreads or a chunkBytes
+ * that is not a multiple of 16.  A chunk larger than the slot payload, or a
+ * tree for a collective other than AllReduce, is clamped when planned (the
+ * plan actually used is reported by vcclCommGetLastPlan). */
 vcclResult_t vcclCommSetTuning(vcclComm_t comm, const vcclTuning_t* tuning);
 
 /* What the most recent launch of the set used (for tests and benchmarks). */
@@ -212,11 +221,16 @@ typedef struct {
                            chains of this many consecutive ranks, double binary tree
                            across the chains; 1 = the plain double binary tree */
 } vcclPlanInfo_t;
+/* Host-side copy; does not synchronise.  All zero before the first launch.
+ * vcclInvalidArgument for an unknown handle or a null info. */
 vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info);
 
 /* Device-side completion time (ns, device wall clock) of each collective of
- * the most recent launch, in issue order; waits for that launch.  n is the
- * capacity of stamps_ns (host array); *written receives the count. */
+ * the most recent launch, in issue order: the latest finish over its ranks.
+ * Waits for that launch.  n is the capacity of stamps_ns (host array,
+ * caller-owned); *written receives the count (0 for n <= 0 or before the
+ * first launch).  vcclInvalidArgument for an unknown handle or a null
+ * pointer. */
 vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int n, int* written);
 
 /* ---------------------------------------------------------------- failure handling
@@ -228,12 +242,19 @@ vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int
 vcclResult_t vcclCommSetTimeout(vcclComm_t comm, uint64_t timeout_us);
 
 /* Test hook: the workgroups of every rank whose bit is set in `mask` skip all
- * their work, so their peers must time out (see vcclCommSetTimeout). */
+ * their work, so their peers must time out (see vcclCommSetTimeout); mask 0
+ * restores normal operation.  Applies to the whole set from its next launch.
+ * Synchronises the device.  vcclInvalidArgument for an unknown handle. */
 vcclResult_t vcclCommDebugSetDeadRanks(vcclComm_t comm, uint32_t mask);
 
 /* Copies `bytes` bytes of the FIFO of connection (channel, receiving rank,
  * connection 0 = ring) for protocol `proto` starting at byte `offset` into the
- * host buffer `dst`.  Synchronises the device.  For line-format checks. */
+ * host buffer `dst` (caller-owned).  Synchronises the device.  For
+ * line-format checks.  vcclInvalidArgument for an unknown handle, a null
+ * dst, channel outside [0, lane limit), rank outside [0, nranks), proto
+ * outside 0..2, or a range that runs past the connection's FIFO
+ * (8 slots of 512 KiB Simple (VCCL_SIMPLE_SLOT_BYTES), 32 KiB LL or
+ * 600 KiB LL128). */
 vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int proto, size_t offset, void* dst,
                                    size_t bytes);
 
@@ -246,11 +267,18 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
  * payload was not.  scope selects the store policy of the lines: 0 device
  * scope (sc1 stores; with pairs = 4 writer and reader sit on different XCDs),
  * 1 XCD scope (plain stores into the shared L2; pairs must be a multiple of 8
- * so that each pair shares an XCD).  Synchronises the device. */
+ * so that each pair shares an XCD).  Synchronises the device; allocates and
+ * frees its own buffers.  vcclInvalidArgument for pairs outside 1..64, lines
+ * outside 1..65536, rounds < 1, a null output, an unknown scope or XCD scope
+ * with pairs not a multiple of 8; vcclRemoteError if a wait ran past its 5 s
+ * bound (the counts are then still written); vcclUnhandledHipError if a HIP
+ * call failed. */
 vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uint64_t* torn, uint64_t* checked);
 
 /* XCC (accelerator die) id of each of `n` workgroups of a plain launch,
- * written to the host array ids[n].  Synchronises the device. */
+ * written to the host array ids[n] (caller-owned).  Synchronises the device.
+ * vcclInvalidArgument for n <= 0 or a null ids; vcclUnhandledHipError if a
+ * HIP call failed. */
 vcclResult_t vcclProbeXccIds(int n, int* ids);
 
 /* ---------------------------------------------------------------- serving
@@ -279,7 +307,13 @@ typedef struct {
 
 /* budgetBytes: device bytes the in-flight requests may hold (their send and
  * receive buffers plus the FIFOs of the lanes they occupy); lanes: concurrent
- * lanes of the persistent kernel (each lane = one workgroup per rank). */
+ * lanes of the persistent kernel (each lane = one workgroup per rank).
+ * comms: the set's handles, as vcclCommInitAll returned them (comms[0] names
+ * the set).  Starts the persistent kernel on a stream of its own.  Errors:
+ * vcclInvalidArgument for a null pointer, lanes < 1 or above the set's lane
+ * limit, or a grid that cannot be resident at once; vcclInvalidUsage if the
+ * set already serves or was aborted.  While a server runs, the set's per-call
+ * API must not be used. */
 vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, vcclServer_t* server);
 /* Non-blocking: queues the request; *id receives its identifier.  Errors,
  * before anything is queued: vcclInvalidArgument for an unknown collective,
@@ -289,14 +323,19 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
  * admitted). */
 vcclResult_t vcclServeSubmit(vcclServer_t server, const vcclRequest_t* req, uint64_t* id);
 /* Makes progress (admits queued requests, retires finished ones) and
- * reports whether `id` has completed; t_done_ns receives the host
- * monotonic time (ns) at which completion was observed. */
+ * reports whether `id` has completed; status (may be NULL) receives the
+ * request's result, vcclInProgress while it runs; t_done_ns (may be NULL)
+ * the host monotonic time (ns) at which completion was observed.  Once
+ * reported done, the id is retired and unknown from then on.
+ * vcclInvalidArgument for a null server or done, or an unknown id. */
 vcclResult_t vcclServeTest(vcclServer_t server, uint64_t id, int* done, vcclResult_t* status, uint64_t* t_done_ns);
 /* Native request loop: submits reqs[i] when arrival_ns[i] nanoseconds have
  * passed since the call began (arrival_ns non-decreasing), keeps making
  * progress, and returns when all n requests completed.  latency_ns[i]
  * receives completion time - arrival time; statuses (may be NULL) the
- * per-request result.  Host arrays of n entries, caller-owned. */
+ * per-request result.  Host arrays of n entries, caller-owned.  A submit
+ * error (as vcclServeSubmit's) returns at once; requests already submitted
+ * stay queued and are drained by vcclServeDestroy. */
 vcclResult_t vcclServeReplay(vcclServer_t server, const vcclRequest_t* reqs, const uint64_t* arrival_ns, int n,
                              uint64_t* latency_ns, vcclResult_t* statuses);
 /* Monitoring: for each of the first maxEntries (lane, rank) pairs,
@@ -308,7 +347,9 @@ vcclResult_t vcclServeReplay(vcclServer_t server, const vcclRequest_t* reqs, con
  * Reads host memory only. */
 #define VCCL_SERVE_DEBUG_WORDS 7
 vcclResult_t vcclServeDebugState(vcclServer_t server, uint64_t* out, int maxEntries);
-/* Drains every request, stops the persistent kernel and frees. */
+/* Drains every request (waiting at most 60 s), stops the persistent kernel,
+ * waits for it and frees the server; the set's per-call API is usable again.
+ * vcclInvalidArgument for a null server. */
 vcclResult_t vcclServeDestroy(vcclServer_t server);
 
 #ifdef __cplusplus

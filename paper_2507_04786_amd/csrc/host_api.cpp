@@ -562,7 +562,7 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
   if (channel < 0 || channel >= c->maxLanes || rank < 0 || rank >= c->nranks || proto < 0 || proto > 2)
     return vcclInvalidArgument;
   const uint64_t fifoBytes = (uint64_t)NSLOTS * c->host.slotBytes[proto];
-  if (offset + bytes > fifoBytes) return vcclInvalidArgument;
+  if (offset > fifoBytes || bytes > fifoBytes - offset) return vcclInvalidArgument;  // no wrap for huge offsets
   const uint64_t id = (uint64_t)channel * c->nranks + rank;
   VCCL_HIPCHECK(hipSetDevice(c->device));
   VCCL_HIPCHECK(hipDeviceSynchronize());
