@@ -297,6 +297,47 @@ def sizes_leg(vccl, torch, comms, sends, recvs, stream):
     return out
 
 
+def large_leg(vccl, torch, comms, sends, stream, sizes_mib=(128, 256), reps=10):
+    """The tuned AllReduce above the headline size: 128 and 256 MiB per rank,
+    where the buffers of all ranks (2-4 GiB each way) no longer fit in the
+    memory-side cache.  Inputs are the headline's N(0,1) buffers tiled on
+    the device.  Kernel time from events on the launch stream, busBW and the
+    HBM fraction of the plan's algorithmic bytes."""
+    R = len(comms)
+    out = {}
+    for mib in sizes_mib:
+        S = mib << 20
+        n = S // 4
+        big_s = [x.repeat((n + x.numel() - 1) // x.numel())[:n].contiguous() for x in sends]
+        big_r = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(R)]
+
+        def issue():
+            for r in range(R):
+                vccl.vcclAllReduce(big_s[r], big_r[r], n, vccl.vcclFloat32, vccl.vcclSum, comms[r], stream)
+
+        for _ in range(2):
+            issue()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            issue()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        err = vccl.vcclCommGetAsyncError(comms[0])
+        if err != vccl.vcclSuccess:
+            raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)}")
+        t = e0.elapsed_time(e1) / reps / 1e3
+        p = vccl.vcclCommGetLastPlan(comms[0])
+        out[str(S)] = {"ms": round(t * 1e3, 4), "busbw_gbs": round(S / t / 1e9 * 2 * (R - 1) / R, 2),
+                       "hbm_frac": round(alg_bytes_per_launch(p, R, S) / t / 1e9 / HBM_PEAK_GBS, 4),
+                       "proto": ["simple", "ll", "ll128"][p["proto"]], "nchannels": p["nchannels"],
+                       "chunk_bytes": p["chunkBytes"]}
+        del big_s, big_r
+        torch.cuda.empty_cache()
+    return out
+
+
 def grouped_leg(vccl, torch, si, comms, stream, reps=10):
     """64 collectives issued in one group against 64 separate launches
     (device time between events on the launch stream, and host wall time)."""
@@ -508,6 +549,7 @@ def main():
 
     protos = {}
     sizes = None
+    large = None
     if not args.no_protocols:
         for name, code in (("simple", vccl.vcclProtoSimple), ("ll", vccl.vcclProtoLL), ("ll128", vccl.vcclProtoLL128)):
             vccl.vcclCommSetTuning(comms[0], algo=vccl.vcclAlgoRing, proto=code)
@@ -520,6 +562,7 @@ def main():
                             "direct": p["direct"]}
         vccl.vcclCommSetTuning(comms[0])
         sizes = sizes_leg(vccl, torch, comms, sends, recvs, stream)
+        large = large_leg(vccl, torch, comms, sends, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -588,6 +631,7 @@ def main():
                      "avg_launch_ms": round(ev_step * 1e3, 4)},
         "protocols": protos,
         "sizes": sizes,
+        "large_sizes": large,
         "collectives_r16": colls16,
         "alltoall": a2a,
         "grouped": grouped,
