@@ -60,12 +60,13 @@ def alg_bytes_per_launch(plan: dict, nranks: int, size: int) -> float:
 
 
 def kernel_source_digest() -> str:
-    """Digest of the kernel's sources (device code and the structures it
-    shares with the host): a recorded counter reading applies while it is
-    unchanged."""
+    """Digest of what decides the launch's memory traffic: the kernel's
+    sources (device code and the structures it shares with the host), the
+    planner and the tuner's table (plan, chunk and store policy).  A recorded
+    counter reading applies while it is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("device.hip", "vccl_dev.h"):
+    for name in ("device.hip", "vccl_dev.h", "host_plan.cpp", "tune_table.inc"):
         with open(os.path.join(ROOT, "paper_2507_04786_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -242,11 +242,12 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   // XCD scope (plain stores into the XCD's L2, sc1 loads) needs the lane map,
   // which claims every lane's roles on one XCD at kernel start; it is the
   // default then, and VCCL_SCOPE=device keeps every store device-coherent
-  // Simple transfers of 8 MiB and more measured 1.5-5.5 % faster with
-  // device-coherent stores (write-through streams instead of dirty L2 lines
-  // written back on eviction); smaller and latency-bound ones up to 9 % (LL,
-  // LL128: up to 25 %) faster in XCD scope.
-  c->deviceScopeBytes = (uint64_t)envLong("VCCL_DEVICE_SCOPE_BYTES", 8 << 20);
+  // XCD scope measured faster for every collective and size (Broadcast up
+  // to 27 %, Reduce up to 13 %: a chain reads back what its predecessor just
+  // wrote, from the shared L2), except Simple AllGathers from 16 MiB, which
+  // ran up to 11 % faster with device-coherent stores.  Send/Recv copies
+  // take device scope from the same size.
+  c->deviceScopeBytes = (uint64_t)envLong("VCCL_DEVICE_SCOPE_BYTES", 16 << 20);
   c->treeSplit = envLong("VCCL_TREE_SPLIT", 1) != 0;
   if (c->xcdMap && envStr("VCCL_SCOPE") != "device") {
     c->host.scope = SCOPE_XCD;

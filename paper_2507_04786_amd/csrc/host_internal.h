@@ -109,7 +109,7 @@ struct Clique {
   std::vector<vcclComm*> handles;
   int occupancy[17] = {0};    // blocks per CU for nthreads = 64 * index
   bool serving = false;       // a persistent serving kernel owns the lanes
-  uint64_t deviceScopeBytes = 0;  // Simple items of collectives this large use device scope
+  uint64_t deviceScopeBytes = 0;  // Simple AllGathers and Send/Recv copies this large use device scope
   bool treeSplit = true;          // split Simple tree channels into concurrent halves
   int ranksPerNode = 1;           // tree topology: chains of this many ranks, trees across them
   uint64_t* claim = nullptr;  // per-XCD role counters (device)

@@ -202,9 +202,11 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   plan->chunkBytes = chunk;
   // halves pay off once a channel pipelines at least two chunks
   plan->split = split && ceilDiv(ceilDiv(S, (uint64_t)nch), chunk) >= 2;
-  // store policy: XCD scope (lower latency) unless a large Simple transfer
-  plan->scope = (c->host.scope == SCOPE_XCD && !(proto == PROTO_SIMPLE && S >= c->deviceScopeBytes))
-                    ? SCOPE_XCD : SCOPE_DEVICE;
+  // store policy: XCD scope (lower latency; data a chain forwards is read
+  // back from the XCD's L2) except for a large Simple AllGather, the one
+  // collective measured faster with write-through stores there
+  const bool devScope = proto == PROTO_SIMPLE && coll.coll == COLL_ALLGATHER && S >= c->deviceScopeBytes;
+  plan->scope = (c->host.scope == SCOPE_XCD && !devScope) ? SCOPE_XCD : SCOPE_DEVICE;
   return vcclSuccess;
 }
 

@@ -1,7 +1,8 @@
 """Measure the plan space and write the tuner's table.
 
 Runs every collective of ``--nranks`` virtual ranks at per-rank sizes
-2^3 .. 2^28 bytes (nccl-tests convention: the larger per-rank buffer) under
+2^3 .. 2^28 bytes (``--min-log2`` / ``--max-log2``; nccl-tests convention:
+the larger per-rank buffer) under
 every (algorithm, protocol, channel count) the planner can choose, for
 Simple from 1 MiB up every chunk of CHUNKS_SIMPLE (0: the planner's formula)
 and for LL / LL128 from 64 KiB up every workgroup size of THREADS_FLAG (0:
@@ -78,7 +79,7 @@ def sweep(args):
         for coll in colls:
             algos = ("ring", "tree") if coll == "allreduce" else ("ring",)
             slow = set()
-            for lg in range(LOG2_MIN, args.max_log2 + 1):
+            for lg in range(args.min_log2, args.max_log2 + 1):
                 S = 1 << lg
                 # count in elements of fp32; AG / RS: size is the larger buffer
                 n = S // 4 // (R if coll in ("allgather", "reducescatter") else 1)
@@ -121,7 +122,8 @@ def sweep(args):
                                 raise RuntimeError(f"device error at {coll} {S} {key}")
                             rec = dict(R=R, coll=coll, S=S, log2=lg, algo=algo, proto=proto, C=C, chunkReq=ck, Treq=th,
                                        Cplan=plan["nchannels"], chunk=plan["chunkBytes"],
-                                       T=plan["nthreads"], direct=plan["direct"], ms=round(ms, 5),
+                                       T=plan["nthreads"], direct=plan["direct"], scope=plan["scope"],
+                                       ms=round(ms, 5),
                                        wall_ms=round(wall * 1e3, 5), reps=reps)
                             out.write(json.dumps(rec) + "\n")
                             if ms > SLOW_MS:
@@ -184,6 +186,7 @@ def main():
     ap.add_argument("--nranks", type=int, default=8)
     ap.add_argument("--out", default="sweep.jsonl")
     ap.add_argument("--colls", default="")
+    ap.add_argument("--min-log2", type=int, default=LOG2_MIN)
     ap.add_argument("--max-log2", type=int, default=LOG2_MAX)
     ap.add_argument("--emit", nargs="*")
     ap.add_argument("--dest", default=os.path.join(HERE, "csrc", "tune_table.inc"))
