@@ -1005,6 +1005,11 @@ __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& a
 
 // Ring Broadcast, Section V-E table: a chain root -> root+1 -> ... -> root-1;
 // root copySend (send in place), middle recvCopySend, last recv.  Bytes.
+// With direct sends the root's copySend would be the chain's slowest stage
+// (a read and two writes per byte, against a read and a write for a middle
+// rank and none for the last): the root's copy into its own receive buffer
+// needs no synchronisation, since the input is there from the start, so the
+// last rank, which otherwise only waits, makes it.
 template <int PROTO, int SC, int DT, int OP>
 __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
   const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
@@ -1014,15 +1019,25 @@ __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& a
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t K = w.chunk;
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
+  const char* rootSend = uniformPtr(args.send[w.root]);
+  char* rootRecv = uniformPtr(args.recv[w.root]);
+  const bool lastCopiesRoot = direct && rootSend != rootRecv;
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
     const uint64_t len = umin(K, w.chCount - a0);
     const uint64_t off = w.chOffset + a0;
     StepArgs a{};
     a.nbytes = len;
     a.dst = uniformPtr(args.recv[me]) + off;
+    if (lastCopiesRoot && pos == R - 1) {
+      PtrList in, out;
+      in.add(rootSend + off);
+      out.add(rootRecv + off);
+      reduceCopyN<DT_U8, OP_COPY, SC>(c, in, out, len);
+    }
     if (pos == 0) {
       a.src = uniformPtr(args.send[me]) + off;
       a.smask = 1;
+      if (lastCopiesRoot) a.dst = nullptr;
     } else {
       a.rmask = 1;
       a.recvDirect = direct;

@@ -8,7 +8,9 @@ Simple from 1 MiB up every chunk of CHUNKS_SIMPLE (0: the planner's formula)
 and for LL / LL128 from 64 KiB up every workgroup size of THREADS_FLAG (0:
 the formula), times each point with HIP events on the launch stream, and
 writes one JSON line per point.  ``--emit`` turns one or more such files into the C++ table the
-planner reads (``csrc/tune_table.inc``).  One table serves collectives
+planner reads (``csrc/tune_table.inc``), keyed by the chunk and workgroup
+size each plan actually ran with: a request of 0 ("the tuner decides")
+resolves to the table the library was built with, not to the formula.  One table serves collectives
 launched alone and in groups: a different plan in a group would change the
 order of a float reduction, and a collective's bits would then depend on its
 grouping.  For every (ranks, collective, size bucket) it holds the fastest
@@ -137,8 +139,22 @@ def sweep(args):
         out.close()
 
 
+def _chunk_col(r):
+    """The chunk the measured plan ran with, for the table's chunk column
+    (Simple from CHUNK_MIN_LOG2 up, else 0 = the formula's).  A request of 0
+    means "the tuner decides", which resolves to the table the library was
+    built with, so the plan's own chunk is what was measured."""
+    return r["chunk"] if r["proto"] == "simple" and r["log2"] >= CHUNK_MIN_LOG2 else 0
+
+
+def _threads_col(r):
+    """The workgroup size the measured plan ran with (LL / LL128 from
+    THREADS_MIN_LOG2 up, else 0), for the same reason."""
+    return r["T"] if r["proto"] != "simple" and r["log2"] >= THREADS_MIN_LOG2 else 0
+
+
 def _plan_key(r):
-    return (r["algo"], r["proto"], r["Cplan"], r.get("chunkReq", 0), r.get("Treq", 0))
+    return (r["algo"], r["proto"], r["Cplan"], _chunk_col(r), _threads_col(r))
 
 
 def pick_best(rows):
@@ -163,13 +179,15 @@ def write_table(best, dest, paths, what):
     lines = ["// Generated by tune_sweep.py --emit from measured sweeps (fp32, sum, tuner-default",
              "// threads); one entry per (ranks, collective, log2 of the per-rank size), " + what + ".",
              "// Fields: nranks, coll, log2 bytes, algo (0 ring, 1 tree), proto (0 Simple, 1 LL,",
-             "// 2 LL128), channels, chunk KiB (0: the planner's formula), threads (0: the formula;",
-             "// used for a collective launched alone), measured microseconds.",
+             "// 2 LL128), channels, chunk KiB (Simple from 1 MiB; 0: the planner's formula),",
+             "// threads (LL / LL128 from 64 KiB, used for a collective launched alone; 0: the",
+             "// formula), measured microseconds.  Chunk and threads are those the measured plan",
+             "// ran with.",
              f"// Sources: {', '.join(os.path.basename(p) for p in paths)}"]
     for (R, coll, lg), r in sorted(best.items(), key=lambda kv: (kv[0][0], COLL_CODE[kv[0][1]], kv[0][2])):
         lines.append("{%d, %d, %d, %d, %d, %d, %d, %d, %.1f}," % (
             R, COLL_CODE[coll], lg, 0 if r["algo"] == "ring" else 1, PROTOS.index(r["proto"]), r["Cplan"],
-            r.get("chunkReq", 0) // 1024, r.get("Treq", 0), r["ms"] * 1e3))
+            _chunk_col(r) // 1024, _threads_col(r), r["ms"] * 1e3))
     open(dest, "w").write("\n".join(lines) + "\n")
     print(f"wrote {len(best)} entries to {dest}")
 

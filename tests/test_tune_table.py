@@ -50,18 +50,23 @@ def test_table_plans_are_legal():
         if r["algo"] == 1:
             assert r["coll"] == 0, f"tree only for AllReduce: {r}"
         assert r["C"] in ts.CHANNELS, r
+        # chunk and threads are those the measured plan ran with: a swept
+        # value or the planner's formula (chunks of 4 KiB granules up to the
+        # Simple slot; workgroups of whole waves)
         if r["chunk_kib"]:
             assert r["proto"] == 0 and r["lg"] >= ts.CHUNK_MIN_LOG2, r
-            assert r["chunk_kib"] * 1024 in ts.CHUNKS_SIMPLE, r
+            assert r["chunk_kib"] % 4 == 0 and 16 <= r["chunk_kib"] <= 512, r
         if r["threads"]:
             assert r["proto"] != 0 and r["lg"] >= ts.THREADS_MIN_LOG2, r
-            assert r["threads"] in ts.THREADS_FLAG, r
+            assert r["threads"] % 64 == 0 and 64 <= r["threads"] <= 1024, r
         assert r["us"] > 0, r
 
 
-def _rec(lg, C, ms, proto="simple", algo="ring", chunk=0, threads=0):
+def _rec(lg, C, ms, proto="simple", algo="ring", chunk=0, threads=0, ran_chunk=128 << 10):
+    """A sweep record; a request of 0 ran with `ran_chunk` (the formula's, or
+    the chunk of the table the library was built with) and 512 threads."""
     return dict(R=8, coll="allreduce", S=1 << lg, log2=lg, algo=algo, proto=proto, C=C, chunkReq=chunk, Treq=threads,
-                Cplan=C, chunk=chunk, T=256, direct=1, ms=ms, wall_ms=ms, reps=3)
+                Cplan=C, chunk=chunk or ran_chunk, T=threads or 512, direct=1, ms=ms, wall_ms=ms, reps=3)
 
 
 def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
@@ -78,7 +83,7 @@ def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
     ts.emit([str(src)], str(dest))
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     got = {int(r[2]): r for r in rows}
-    assert got[small][3:8] == ("0", "0", "8", "0", "0")     # ring Simple, 8 channels, formulas
+    assert got[small][3:8] == ("0", "0", "8", "128", "0")   # ring Simple, 8 channels, the chunk it ran
     assert got[large][3:8] == ("0", "1", "8", "0", "1024")  # LL at 8 channels: within 3 %, fewer
     # without the LL point the 32-channel plan with its 64 KiB chunk wins
     src.write_text("\n".join(json.dumps(r) for r in recs if r["proto"] == "simple") + "\n")
@@ -86,3 +91,21 @@ def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     got = {int(r[2]): r for r in rows}
     assert got[large][3:8] == ("0", "0", "32", "64", "0")
+
+
+def test_emit_uses_the_chunk_a_default_request_ran_with(tmp_path):
+    """A request of chunk 0 resolves to the table the library was built
+    with: a record that asked for 0 but ran with 32 KiB is the same plan as
+    one that asked for 32 KiB, is averaged with it, and is emitted as
+    32 KiB, not as the formula's chunk."""
+    lg = 26
+    recs = [_rec(lg, 32, 0.41, chunk=0, ran_chunk=32 << 10), _rec(lg, 32, 0.43, chunk=32 << 10),
+            _rec(lg, 32, 0.46, chunk=64 << 10)]
+    src = tmp_path / "sweep.jsonl"
+    src.write_text("\n".join(json.dumps(r) for r in recs) + "\n")
+    dest = tmp_path / "table.inc"
+    ts.emit([str(src)], str(dest))
+    rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
+    assert len(rows) == 1
+    assert rows[0][3:8] == ("0", "0", "32", "32", "0")
+    assert float(rows[0][8]) == 420.0  # the two runs of that plan averaged
