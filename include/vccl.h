@@ -183,7 +183,7 @@ vcclResult_t vcclGroupEnd(void);
  * Section III-D and Section II-C: the algorithm and protocol are chosen per
  * call (user setting, else a tuning model), then the channel count.  The
  * library's tuner takes algorithm, protocol, channels, chunk (Simple) and
- * workgroup size (LL / LL128, for a collective launched alone) from a table
+ * workgroup size (for a collective launched alone) from a table
  * measured on this device for 4, 8 and 16 ranks and power-of-two sizes,
  * using the nearest entry.  These calls and the environment variables
  * VCCL_ALGO, VCCL_PROTO (simple|ll|ll128), VCCL_NCHANNELS, VCCL_CHUNK_BYTES,

@@ -5,8 +5,8 @@ Runs every collective of ``--nranks`` virtual ranks at per-rank sizes
 the larger per-rank buffer) under
 every (algorithm, protocol, channel count) the planner can choose, for
 Simple from 1 MiB up every chunk of CHUNKS_SIMPLE (0: the planner's formula)
-and for LL / LL128 from 64 KiB up every workgroup size of THREADS_FLAG (0:
-the formula), times each point with HIP events on the launch stream, and
+and workgroup size of THREADS_SIMPLE, for LL / LL128 from 64 KiB up every
+workgroup size of THREADS_FLAG (0: the formula), times each point with HIP events on the launch stream, and
 writes one JSON line per point.  ``--emit`` turns one or more such files into the C++ table the
 planner reads (``csrc/tune_table.inc``), keyed by the chunk and workgroup
 size each plan actually ran with: a request of 0 ("the tuner decides")
@@ -40,6 +40,7 @@ CHANNELS = (1, 2, 4, 8, 16, 32, 64)  # 64 where the communicator's lane limit al
 CHUNKS_SIMPLE = (0, 32 << 10, 64 << 10, 256 << 10)
 CHUNK_MIN_LOG2 = 20
 THREADS_FLAG = (0, 256, 1024)  # 0: the formula (512 from 256 KiB, else 256)
+THREADS_SIMPLE = (0, 1024)  # Simple from CHUNK_MIN_LOG2 up; 0: the formula's 256
 THREADS_MIN_LOG2 = 16
 LOG2_MIN, LOG2_MAX = 3, 28
 SLOW_MS = 4.0   # a plan slower than this at one size is not tried at larger sizes
@@ -90,7 +91,10 @@ def sweep(args):
                 for algo in algos:
                     for proto in PROTOS:
                         chunks = CHUNKS_SIMPLE if (proto == "simple" and lg >= CHUNK_MIN_LOG2) else (0,)
-                        threads = THREADS_FLAG if (proto != "simple" and lg >= THREADS_MIN_LOG2) else (0,)
+                        if proto == "simple":
+                            threads = THREADS_SIMPLE if lg >= CHUNK_MIN_LOG2 else (0,)
+                        else:
+                            threads = THREADS_FLAG if lg >= THREADS_MIN_LOG2 else (0,)
                         for C, ck, th in [(C, ck, th) for C in CHANNELS for ck in chunks for th in threads]:
                             key = (algo, proto, C, ck, th)
                             if key in slow:
@@ -149,8 +153,10 @@ def _chunk_col(r):
 
 def _threads_col(r):
     """The workgroup size the measured plan ran with (LL / LL128 from
-    THREADS_MIN_LOG2 up, else 0), for the same reason."""
-    return r["T"] if r["proto"] != "simple" and r["log2"] >= THREADS_MIN_LOG2 else 0
+    THREADS_MIN_LOG2 up, Simple from CHUNK_MIN_LOG2 up, else 0), for the
+    same reason."""
+    lo = CHUNK_MIN_LOG2 if r["proto"] == "simple" else THREADS_MIN_LOG2
+    return r["T"] if r["log2"] >= lo else 0
 
 
 def _plan_key(r):
@@ -180,9 +186,9 @@ def write_table(best, dest, paths, what):
              "// threads); one entry per (ranks, collective, log2 of the per-rank size), " + what + ".",
              "// Fields: nranks, coll, log2 bytes, algo (0 ring, 1 tree), proto (0 Simple, 1 LL,",
              "// 2 LL128), channels, chunk KiB (Simple from 1 MiB; 0: the planner's formula),",
-             "// threads (LL / LL128 from 64 KiB, used for a collective launched alone; 0: the",
-             "// formula), measured microseconds.  Chunk and threads are those the measured plan",
-             "// ran with.",
+             "// threads (LL / LL128 from 64 KiB, Simple from 1 MiB; used for a collective launched",
+             "// alone; 0: the formula), measured microseconds.  Chunk and threads are those the",
+             "// measured plan ran with.",
              f"// Sources: {', '.join(os.path.basename(p) for p in paths)}"]
     for (R, coll, lg), r in sorted(best.items(), key=lambda kv: (kv[0][0], COLL_CODE[kv[0][1]], kv[0][2])):
         lines.append("{%d, %d, %d, %d, %d, %d, %d, %d, %.1f}," % (

@@ -57,16 +57,18 @@ def test_table_plans_are_legal():
             assert r["proto"] == 0 and r["lg"] >= ts.CHUNK_MIN_LOG2, r
             assert r["chunk_kib"] % 4 == 0 and 16 <= r["chunk_kib"] <= 512, r
         if r["threads"]:
-            assert r["proto"] != 0 and r["lg"] >= ts.THREADS_MIN_LOG2, r
+            assert r["lg"] >= (ts.CHUNK_MIN_LOG2 if r["proto"] == 0 else ts.THREADS_MIN_LOG2), r
             assert r["threads"] % 64 == 0 and 64 <= r["threads"] <= 1024, r
         assert r["us"] > 0, r
 
 
 def _rec(lg, C, ms, proto="simple", algo="ring", chunk=0, threads=0, ran_chunk=128 << 10):
     """A sweep record; a request of 0 ran with `ran_chunk` (the formula's, or
-    the chunk of the table the library was built with) and 512 threads."""
+    the chunk of the table the library was built with) and the formula's
+    workgroup (256 threads for Simple, 512 for LL / LL128 at these sizes)."""
     return dict(R=8, coll="allreduce", S=1 << lg, log2=lg, algo=algo, proto=proto, C=C, chunkReq=chunk, Treq=threads,
-                Cplan=C, chunk=chunk or ran_chunk, T=threads or 512, direct=1, ms=ms, wall_ms=ms, reps=3)
+                Cplan=C, chunk=chunk or ran_chunk, T=threads or (256 if proto == "simple" else 512), direct=1, ms=ms,
+                wall_ms=ms, reps=3)
 
 
 def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
@@ -83,14 +85,14 @@ def test_emit_prefers_fewer_channels_within_tolerance(tmp_path):
     ts.emit([str(src)], str(dest))
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     got = {int(r[2]): r for r in rows}
-    assert got[small][3:8] == ("0", "0", "8", "128", "0")   # ring Simple, 8 channels, the chunk it ran
+    assert got[small][3:8] == ("0", "0", "8", "128", "256")  # ring Simple, 8 channels, the chunk it ran
     assert got[large][3:8] == ("0", "1", "8", "0", "1024")  # LL at 8 channels: within 3 %, fewer
     # without the LL point the 32-channel plan with its 64 KiB chunk wins
     src.write_text("\n".join(json.dumps(r) for r in recs if r["proto"] == "simple") + "\n")
     ts.emit([str(src)], str(dest))
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     got = {int(r[2]): r for r in rows}
-    assert got[large][3:8] == ("0", "0", "32", "64", "0")
+    assert got[large][3:8] == ("0", "0", "32", "64", "256")
 
 
 def test_emit_uses_the_chunk_a_default_request_ran_with(tmp_path):
@@ -107,5 +109,5 @@ def test_emit_uses_the_chunk_a_default_request_ran_with(tmp_path):
     ts.emit([str(src)], str(dest))
     rows = [ROW.match(line.strip()).groups() for line in open(dest) if line.startswith("{")]
     assert len(rows) == 1
-    assert rows[0][3:8] == ("0", "0", "32", "32", "0")
+    assert rows[0][3:8] == ("0", "0", "32", "32", "256")
     assert float(rows[0][8]) == 420.0  # the two runs of that plan averaged
