@@ -353,6 +353,42 @@ def test_reduce_leaves_non_root_untouched(vccl, comms_for):
         assert (recvs[r].view(t.uint8) == 0x77).all().item()
 
 
+def test_zero_counts_are_no_ops(vccl, comms_for):
+    """A count of 0 is a legal call (null buffers allowed, as in the per-call
+    API of Section II-A): it is matched across ranks like any other call,
+    launches nothing and writes nothing; inside a group it leaves the
+    group's other work intact (one collective in the launch)."""
+    R = 4
+    comms = comms_for(R)
+    t = H.torch()
+    for coll in ("allreduce", "reducescatter", "allgather", "broadcast", "reduce"):
+        H.call(vccl, comms, coll, [None] * R, [None] * R, 0, "float32", "sum", 1)
+    vccl.vcclSend(None, 0, vccl.vcclInt32, 1, comms[0])
+    vccl.vcclRecv(None, 0, vccl.vcclInt32, 0, comms[1])
+    t.cuda.synchronize()
+    assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+    n = 1000
+    xs = _inputs(R, "int32", n, extra=71)
+    sends = [H.to_dev(x) for x in xs]
+    recvs = [H.empty_dev(n, "int32") for _ in range(R)]
+    guard = [H.empty_dev(64, "int32") for _ in range(R)]
+    vccl.vcclGroupStart()
+    H.call(vccl, comms, "allgather", sends, guard, 0, "int32")
+    H.call(vccl, comms, "allreduce", sends, recvs, n, "int32")
+    H.call(vccl, comms, "broadcast", sends, guard, 0, "int32", root=2)
+    vccl.vcclSend(sends[3], 0, vccl.vcclInt32, 2, comms[3])
+    vccl.vcclRecv(guard[2], 0, vccl.vcclInt32, 3, comms[2])
+    vccl.vcclGroupEnd()
+    t.cuda.synchronize()
+    assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+    assert vccl.vcclCommGetLastPlan(comms[0])["ncolls"] == 1
+    want = defs.allreduce(xs, "sum", "int32")
+    for r in range(R):
+        _assert_bits(H.from_dev(recvs[r], "int32"), want[r], f"allreduce beside zero counts, rank {r}")
+        g = H.from_dev(guard[r], "int32").view(np.uint32)
+        assert (g == 0x5A5A5A5A).all(), f"a zero-count call wrote rank {r}'s buffer"
+
+
 def test_large_allreduce_sampled_and_bounded(vccl, comms_for):
     """8 ranks, fp32 N(0,1), 64 MiB per rank: sampled elements against the
     oracle's closed-form fold, every element against the fp64 sum within
