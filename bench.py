@@ -207,7 +207,9 @@ def collectives_leg(vccl, torch, si, R=16, size=64 << 20, steps=10):
 def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):
     """All-to-all through grouped Send/Recv: R ranks, fp32, `size` bytes per
     rank (R blocks of size / R), one group of R * R transfers per step.
-    Algorithmic bytes: every byte is read once and written once, 2 R size."""
+    Algorithmic bytes: every byte is read once and written once, 2 R size.
+    `ms` is the launch on the device (staging copies and kernel);
+    `host_inclusive_ms` adds the host's issue and planning of the group."""
     import numpy as np
     n = size // 4 // R
     xs = si.rank_inputs(si.WL_P2P, R, "float32", 1 << 20)
@@ -232,15 +234,30 @@ def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):
         for _ in range(2):
             issue()
         torch.cuda.synchronize()
-        # the launch's own duration: events around GroupEnd (the 2 R^2 calls
-        # before it are host work, ~0.3 ms of Python per group)
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         t0 = time.perf_counter()
         for k in range(steps):
             issue(evs[k])
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
-        t = float(np.median([a.elapsed_time(b) for a, b in evs])) / 1e3
+        # the launch's own duration on the device: each group's events
+        # queued behind a spin kernel (about 0.3 ms) that keeps the device
+        # busy while GroupEnd plans the 2 R^2 calls on the host, so they
+        # bracket the staging copies and the kernel only
+        dev = []
+        for k in range(steps):
+            vccl.vcclGroupStart()
+            for a in range(R):
+                for b in range(R):
+                    vccl.vcclSend(sends[a][b * n:(b + 1) * n], n, vccl.vcclFloat32, b, comms[a], stream)
+                    vccl.vcclRecv(recvs[b][a * n:(a + 1) * n], n, vccl.vcclFloat32, a, comms[b], stream)
+            torch.cuda._sleep(200_000)
+            evs[k][0].record(stream)
+            vccl.vcclGroupEnd()
+            evs[k][1].record(stream)
+            torch.cuda.synchronize()
+            dev.append(evs[k][0].elapsed_time(evs[k][1]))
+        t = float(np.median(dev)) / 1e3
         err = vccl.vcclCommGetAsyncError(comms[0])
         if err != vccl.vcclSuccess:
             raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)} in all-to-all")
