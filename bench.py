@@ -13,9 +13,11 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
   sizes       the AllReduce at 8 B .. 16 MiB per rank, tuner plan and each
               protocol forced: us per call (issued from Python), busBW, HBM
               fraction
+  large_sizes the tuned AllReduce at 128 and 256 MiB per rank
   collectives_r16  every collective (and the tree AllReduce) at 16 ranks, bf16,
               64 MiB per rank: busBW and HBM fraction
-  alltoall    grouped Send/Recv between all 8 x 8 rank pairs, 64 MiB per rank
+  alltoall    grouped Send/Recv between all 8 x 8 rank pairs, 64 MiB per rank:
+              the launch's device time and the host-inclusive time
   grouped     64 mixed collectives (AR/AG/RS, 4 KiB..16 MiB log-uniform, fp32 /
               bf16 / int32) in one GroupStart/GroupEnd launch against one
               launch per collective, and the same for a batch of sub-1 MiB

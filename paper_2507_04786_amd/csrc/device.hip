@@ -80,7 +80,9 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // Memory policy of everything that passes between the workgroups of a lane:
 // chunks and direct writes (Simple), counters, LL units and LL128 lines
-// (DevComm::scope).  Loads are always device-scope coherent (sc1): they skip
+// (WorkItem::scope, chosen per item by the planner; DevComm::scope forces
+// device scope for the whole set).  Loads are always device-scope coherent
+// (sc1): they skip
 // the CU cache and read the XCD's L2, or memory when the line is not there.
 //  SCOPE_DEVICE: stores are device-scope coherent too (sc1), so they reach
 //    memory and a reader on any XCD sees them.

@@ -45,7 +45,9 @@ static uint64_t maxChunkBytes(const Clique* c, int proto) {
 // size) the fastest (algorithm, protocol, channels, chunk, threads) of a
 // sweep over all of them on this chip (fewest channels among plans within
 // 10 % of the best below 16 MiB, within 3 % from 16 MiB up).  chunkKiB and
-// nthreads 0: the formulas below.
+// nthreads hold what the measured plan ran with (Simple chunks and workgroup
+// sizes from 1 MiB, LL / LL128 workgroup sizes from 64 KiB); 0: the formulas
+// below.
 struct TuneEntry {
   int nranks, coll, log2, algo, proto, nchannels, chunkKiB, nthreads;
   float us;
@@ -151,8 +153,8 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   if (proto == PROTO_LL128 && S >= (16u << 20)) dfltT = 1024;
   if (proto == PROTO_SIMPLE) dfltT = 256;
   // the table's workgroup size, for a collective launched alone (a group runs
-  // every item at the largest size among its plans; the size never changes
-  // a result's bits)
+  // every item at the largest formula size among its plans, measured faster
+  // than the table's; the size never changes a result's bits)
   if (single && te && te->nthreads > 0 && te->algo == algo && te->proto == proto) dfltT = te->nthreads;
   int nthreads = (int)pickPos(c->apiTune.nthreads, c->envTune.nthreads, dfltT);
   nthreads = std::max(64, std::min(1024, nthreads / 64 * 64));

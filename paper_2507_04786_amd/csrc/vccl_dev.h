@@ -43,9 +43,11 @@ constexpr uint32_t CTR_RECORD_U64 = 32;  // 256 B per connection
 constexpr uint32_t CTR_HEAD_U64 = 16;    // head at +128 B
 constexpr uint32_t CLAIM_STRIDE_U64 = 16;
 
-// Scope of the Simple protocol's bulk data traffic between the workgroups of
-// a lane (see device.hip): SCOPE_DEVICE -- anywhere on the device;
-// SCOPE_XCD -- through one XCD's L2.  Flags and counters: device scope.
+// Store policy of a work item's traffic between the workgroups of a lane
+// (data, protocol lines and step counters; see device.hip): SCOPE_DEVICE --
+// sc1 stores, seen from any XCD; SCOPE_XCD -- plain stores into the L2 of
+// the XCD the lane's workgroups share.  Loads are device-coherent (sc1)
+// under both.
 constexpr uint32_t SCOPE_DEVICE = 0, SCOPE_XCD = 1;
 
 // device-side error codes (bit flags in the error word)
