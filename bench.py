@@ -132,7 +132,8 @@ def coll_alg_bytes(coll, plan, R, size):
     AllReduce as alg_bytes_per_launch; ReduceScatter / AllGather with block
     b = size / R: R [R + 1 + 2f(R-1)] b, or R (2R - 1) b for a direct
     AllGather; Broadcast / Reduce: [R + 1 + 2f(R-1)] size, or (2R - 1) size
-    for a direct Broadcast."""
+    for a direct Broadcast (the step table's bytes; the kernel, whose last
+    rank makes the root's local copy, reads the root's input once more)."""
     f = {0: 1.0, 1: 2.0, 2: 16.0 / 15.0}[plan["proto"]]
     direct = plan["proto"] == 0 and plan["direct"]
     if coll == "allreduce":
