@@ -573,10 +573,10 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
 vcclResult_t vcclProbeXccIds(int n, int* ids) {
   if (n <= 0 || !ids) return vcclInvalidArgument;
   int* d = nullptr;
-  VCCL_HIPCHECK(hipMalloc((void**)&d, n * sizeof(int)));
+  VCCL_HIPCHECK(hipMalloc((void**)&d, (size_t)n * sizeof(int)));
   hipError_t e = vcclLaunchXccProbe(d, n, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(ids, d, n * sizeof(int), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(ids, d, (size_t)n * sizeof(int), hipMemcpyDeviceToHost);
   hipFree(d);
   if (e != hipSuccess) {
     logError("xcc probe", e, __FILE__, __LINE__);
@@ -595,28 +595,30 @@ vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uin
   unsigned long long* counts = nullptr;
   uint32_t* failed = nullptr;
   const size_t bytes = (size_t)pairs * lines * LL128_LINE;
-  VCCL_HIPCHECK(hipMalloc((void**)&bufs, bytes));
-  VCCL_HIPCHECK(hipMalloc((void**)&acks, (size_t)pairs * 32 * sizeof(uint64_t)));
-  VCCL_HIPCHECK(hipMalloc((void**)&counts, 2 * sizeof(unsigned long long)));
-  VCCL_HIPCHECK(hipMalloc((void**)&failed, sizeof(uint32_t)));
-  VCCL_HIPCHECK(hipMemset(bufs, 0, bytes));
-  VCCL_HIPCHECK(hipMemset(acks, 0, (size_t)pairs * 32 * sizeof(uint64_t)));
-  VCCL_HIPCHECK(hipMemset(counts, 0, 2 * sizeof(unsigned long long)));
-  VCCL_HIPCHECK(hipMemset(failed, 0, sizeof(uint32_t)));
+  const size_t ackBytes = (size_t)pairs * 32 * sizeof(uint64_t);
+  // every buffer is freed on every path below
+  hipError_t e = hipMalloc((void**)&bufs, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&acks, ackBytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&counts, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&failed, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(bufs, 0, bytes);
+  if (e == hipSuccess) e = hipMemset(acks, 0, ackBytes);
+  if (e == hipSuccess) e = hipMemset(counts, 0, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(failed, 0, sizeof(uint32_t));
   int dev = 0, wallKHz = 100000;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, dev);
   const uint64_t maxTicks = (uint64_t)wallKHz * 1000ull * 5ull;  // 5 s per wait
-  hipError_t e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, scope, nullptr);
+  if (e == hipSuccess) e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, scope, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   unsigned long long h[2] = {0, 0};
   uint32_t hf = 0;
   if (e == hipSuccess) e = hipMemcpy(h, counts, sizeof(h), hipMemcpyDeviceToHost);
   if (e == hipSuccess) e = hipMemcpy(&hf, failed, sizeof(hf), hipMemcpyDeviceToHost);
-  hipFree(bufs);
-  hipFree(acks);
-  hipFree(counts);
-  hipFree(failed);
+  if (bufs) hipFree(bufs);
+  if (acks) hipFree(acks);
+  if (counts) hipFree(counts);
+  if (failed) hipFree(failed);
   if (e != hipSuccess) {
     logError("tear probe", e, __FILE__, __LINE__);
     return vcclUnhandledHipError;
