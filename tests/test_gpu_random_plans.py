@@ -2,7 +2,8 @@
 
 Each case draws a rank count, a collective, a dtype and op, a protocol, an
 algorithm (the tree for AllReduce), a channel count, a chunk, a workgroup
-size and a ragged count, runs it on the device with that tuning, and
+size and a ragged count (Simple: direct copies into peer buffers on every
+other case), runs it on the device with that tuning, and
 compares every rank's output bit for bit with the oracle run on the plan the
 library reports (channels and chunk after its clamps).  The combinations go
 beyond the fixed matrices: odd rank counts with trees and chains, 64- and
@@ -66,7 +67,7 @@ def test_random_plans_match_oracle(vccl):
         for (i, R, coll, dtype, op, proto, algo, C, T, chunk, n, root) in sorted(cases(), key=lambda c: (c[1], c[0])):
             C = min(C, lane_limit(ncus, R))
             print(f"case {i}: R={R} {coll} {dtype} {op} {proto} {algo} C={C} T={T} chunk={chunk} n={n} "
-                  f"root={root}", flush=True)
+                  f"root={root} direct={int(proto == 'simple' and i % 2 == 0)}", flush=True)
             if R not in comm_sets:
                 for comms in comm_sets.values():
                     for c in comms:
@@ -80,12 +81,16 @@ def test_random_plans_match_oracle(vccl):
                 xs = si.rank_inputs(si.WL_TREE_AND_CHAINS, R, dtype, sn, extra=1000 + i)
             sends = [H.to_dev(x) for x in xs]
             recvs = [H.empty_dev(H.recv_len(coll, n, R), dtype) for _ in range(R)]
-            H.tune(vccl, comms, algo, proto, nchannels=C, chunk=chunk, nthreads=T)
+            # direct copies (Simple) on every other case: the results do not
+            # depend on them, the paths they take do
+            direct = int(proto == "simple" and i % 2 == 0)
+            H.tune(vccl, comms, algo, proto, nchannels=C, chunk=chunk, nthreads=T, direct=direct)
             try:
                 H.call(vccl, comms, coll, sends, recvs, n, dtype, op, root)
                 t.cuda.synchronize()
                 assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess, f"case {i}"
                 plan = vccl.vcclCommGetLastPlan(comms[0])
+                assert plan["direct"] == direct, f"case {i}: direct {direct} requested, plan {plan}"
             finally:
                 H.untune(vccl, comms)
             got = [H.from_dev(r, dtype) for r in recvs]
