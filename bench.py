@@ -244,7 +244,7 @@ def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
         # the launch's own duration on the device: each group's events
-        # queued behind a spin kernel (about 0.3 ms) that keeps the device
+        # queued behind a spin kernel (about 1.5 ms) that keeps the device
         # busy while GroupEnd plans the 2 R^2 calls on the host, so they
         # bracket the staging copies and the kernel only
         dev = []
@@ -254,7 +254,7 @@ def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):
                 for b in range(R):
                     vccl.vcclSend(sends[a][b * n:(b + 1) * n], n, vccl.vcclFloat32, b, comms[a], stream)
                     vccl.vcclRecv(recvs[b][a * n:(a + 1) * n], n, vccl.vcclFloat32, a, comms[b], stream)
-            torch.cuda._sleep(200_000)
+            torch.cuda._sleep(1_000_000)
             evs[k][0].record(stream)
             vccl.vcclGroupEnd()
             evs[k][1].record(stream)
