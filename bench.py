@@ -362,8 +362,10 @@ def large_leg(vccl, torch, comms, sends, stream, sizes_mib=(128, 256), reps=10):
 
 
 def grouped_leg(vccl, torch, si, comms, stream, reps=10):
-    """64 collectives issued in one group against 64 separate launches
-    (device time between events on the launch stream, and host wall time)."""
+    """64 collectives issued in one group against 64 separate launches:
+    time between events on the launch stream around the issue (the host's
+    issue and planning included, as a caller sees it), host wall time, and
+    the device's own time with the launches queued behind a spin kernel."""
     import numpy as np
     R = len(comms)
     arenas = _send_arenas(torch, si, si.WL_GROUPED, R, 16 << 20)
@@ -407,12 +409,33 @@ def grouped_leg(vccl, torch, si, comms, stream, reps=10):
                 dev.append(e0.elapsed_time(e1) / 1e3)
             return float(np.median(dev)), float(np.median(wall))
 
+        def device_only(group):
+            # the launches queued behind a spin kernel (about 3 ms) that keeps
+            # the device busy while the host issues and plans them, so the
+            # events bracket device work only
+            spin = getattr(torch.cuda, "_sleep", None)
+            if spin is None:
+                return None
+            dev = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                spin(2_000_000)
+                e0.record(stream)
+                issue(group)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                dev.append(e0.elapsed_time(e1) / 1e3)
+            return float(np.median(dev))
+
         pc_dev, pc_wall = timed(False)
+        pc_only = device_only(False)
         snap = [[x.clone() for x in rr] for rr in recvs]
         for rr in recvs:
             for x in rr:
                 x.fill_(0x5A)
         g_dev, g_wall = timed(True)
+        g_only = device_only(True)
         plan = vccl.vcclCommGetLastPlan(comms[0])
         same = all(bool(torch.equal(a, b)) for ra, rb in zip(snap, recvs) for a, b in zip(ra, rb))
         err = vccl.vcclCommGetAsyncError(comms[0])
@@ -423,7 +446,11 @@ def grouped_leg(vccl, torch, si, comms, stream, reps=10):
                         "sub_1MiB_fraction": round(float(np.mean([x < (1 << 20) for x in sizes])), 3),
                         "grouped_ms": round(g_dev * 1e3, 4), "per_call_ms": round(pc_dev * 1e3, 4),
                         "grouped_wall_ms": round(g_wall * 1e3, 4), "per_call_wall_ms": round(pc_wall * 1e3, 4),
-                        "speedup": round(pc_dev / g_dev, 3), "lanes": plan["nlanes"],
+                        "speedup": round(pc_dev / g_dev, 3),
+                        "grouped_device_ms": None if g_only is None else round(g_only * 1e3, 4),
+                        "per_call_device_ms": None if pc_only is None else round(pc_only * 1e3, 4),
+                        "device_speedup": None if not (g_only and pc_only) else round(pc_only / g_only, 3),
+                        "lanes": plan["nlanes"],
                         "grouped_equals_per_call": same}
         del recvs, snap
     return result
