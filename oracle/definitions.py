@@ -105,10 +105,13 @@ def exact_sum(values):
 
 
 def unit_roundoff(dtype):
+    """Relative error of one reduction hop.  A bf16 hop rounds twice (the fp32
+    sum to fp32, then that to bf16), so its factor is
+    (1 + 2^-24)(1 + 2^-8) = 1 + 2^-8 + 2^-24 + 2^-32."""
     if dtype == "float32":
         return 2.0 ** -24
     if dtype == "bfloat16":
-        return 2.0 ** -8 + 2.0 ** -24
+        return 2.0 ** -8 + 2.0 ** -24 + 2.0 ** -32
     raise ValueError(dtype)
 
 

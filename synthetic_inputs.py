@@ -14,9 +14,10 @@ Element types and their storage:
 * ``int32``    -> ``numpy.int32``, uniform integers in ``[lo, hi]``.
 * ``float32``  -> ``numpy.float32``, standard normal N(0, 1) or uniform.
 * ``bfloat16`` -> ``numpy.uint16`` holding the bf16 bit pattern.  Values are
-  drawn as float32 U(-1, 1) and the upper 16 bits are kept (truncation toward
-  zero), which yields bf16 values in (-1, 1).  Truncation is a property of the
-  generator only; it plays no part in the collectives' own rounding.
+  drawn as float32 U(-1, 1) and rounded to the nearest bf16 (ties to even),
+  which yields bf16 values in [-1, 1].  The conversion belongs to the
+  generator only (it shapes the input distribution); the collectives'
+  own rounding is not done here.
 """
 from __future__ import annotations
 
@@ -60,8 +61,17 @@ def draw(dtype: str, n: int, rng: np.random.Generator, dist: str | None = None,
         return rng.uniform(-1.0, 1.0, size=n).astype(np.float32)
     if dtype == "bfloat16":
         f = rng.uniform(-1.0, 1.0, size=n).astype(np.float32)
-        return (f.view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+        return _bf16_nearest(f)
     raise ValueError(f"unknown dtype {dtype}")
+
+
+def _bf16_nearest(f: np.ndarray) -> np.ndarray:
+    """bf16 bit patterns of the finite float32 values f, rounded to nearest,
+    ties to even: add just under half a bf16 ulp (plus one when the kept part
+    is odd) and drop the low 16 bits."""
+    u = np.asarray(f, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    odd = (u >> np.uint64(16)) & np.uint64(1)
+    return ((u + np.uint64(0x7FFF) + odd) >> np.uint64(16)).astype(np.uint16)
 
 
 def rank_inputs(workload_id: int, nranks: int, dtype: str, n: int,
