@@ -361,103 +361,173 @@ def large_leg(vccl, torch, comms, sends, stream, sizes_mib=(128, 256), reps=10):
     return out
 
 
-def grouped_leg(vccl, torch, si, comms, stream, reps=10):
-    """64 collectives issued in one group against 64 separate launches:
-    time between events on the launch stream around the issue (the host's
-    issue and planning included, as a caller sees it), host wall time, and
-    the device's own time with the launches queued behind a spin kernel."""
+def grouped_leg(vccl, torch, si, comms, stream, seeds=10, reps=3):
+    """64 collectives issued in one group against 64 separate launches, over
+    `seeds` seeded batches.  Per batch: the time from the first call's issue
+    to the last kernel's end (events on the launch stream, the host's issue
+    and planning included, as a caller sees it) and the same with the
+    launches queued behind a spin kernel (device time only).  Per
+    collective: its completion latency from the batch's start -- per-call,
+    an event after each launch; grouped, the launch's end less the time by
+    which the collective's own completion stamp (the device clock, latest
+    over its ranks) precedes the last one.  p50 / p99 over the sub-1 MiB
+    collectives of all batches, both paths, both timings.  The two paths'
+    outputs are compared bit for bit on every batch."""
     import numpy as np
     R = len(comms)
     arenas = _send_arenas(torch, si, si.WL_GROUPED, R, 16 << 20)
     codes = {"float32": vccl.vcclFloat32, "bfloat16": vccl.vcclBfloat16, "int32": vccl.vcclInt32}
-    result = {}
+    spin = getattr(torch.cuda, "_sleep", None)
+    result = {"seeds": seeds, "reps_per_seed": reps}
     for name, lo, hi in (("mixed_4KiB_16MiB", 4 << 10, 16 << 20), ("sub_1MiB", 4 << 10, 1 << 20)):
-        specs = _batch_specs(si, 1, 64, lo, hi, R)
-        recvs = []
-        for coll, dt, n in specs:
-            rl = n * R if coll == "allgather" else n
-            recvs.append([torch.empty(rl * ELEM[dt], dtype=torch.uint8, device="cuda") for _ in range(R)])
+        tot = {(g, d): [] for g in (0, 1) for d in (0, 1)}
+        lat = {(g, d): [] for g in (0, 1) for d in (0, 1)}
+        same, nbytes, nsub, ncoll, lanes = True, 0, 0, 0, 0
+        for seed in range(1, seeds + 1):
+            specs = _batch_specs(si, seed, 64, lo, hi, R)
+            sizes = [n * ELEM[dt] * (R if c != "allreduce" else 1) for c, dt, n in specs]
+            small = np.array([x < (1 << 20) for x in sizes])
+            nbytes += int(sum(sizes))
+            nsub += int(small.sum())
+            ncoll += len(specs)
+            recvs = []
+            for coll, dt, n in specs:
+                rl = n * R if coll == "allgather" else n
+                recvs.append([torch.empty(rl * ELEM[dt], dtype=torch.uint8, device="cuda") for _ in range(R)])
 
-        def issue(group):
-            if group:
-                vccl.vcclGroupStart()
-            for k, (coll, dt, n) in enumerate(specs):
+            def issue_one(k):
+                coll, dt, n = specs[k]
                 for r in range(R):
-                    s, d = arenas[dt][r], recvs[k][r]
+                    sb, d = arenas[dt][r], recvs[k][r]
                     if coll == "allreduce":
-                        vccl.vcclAllReduce(s, d, n, codes[dt], vccl.vcclSum, comms[r], stream)
+                        vccl.vcclAllReduce(sb, d, n, codes[dt], vccl.vcclSum, comms[r], stream)
                     elif coll == "allgather":
-                        vccl.vcclAllGather(s, d, n, codes[dt], comms[r], stream)
+                        vccl.vcclAllGather(sb, d, n, codes[dt], comms[r], stream)
                     else:
-                        vccl.vcclReduceScatter(s, d, n, codes[dt], vccl.vcclSum, comms[r], stream)
-            if group:
-                vccl.vcclGroupEnd()
+                        vccl.vcclReduceScatter(sb, d, n, codes[dt], vccl.vcclSum, comms[r], stream)
 
-        def timed(group):
-            issue(group)
-            torch.cuda.synchronize()
-            dev, wall = [], []
-            for _ in range(reps):
+            def batch(group, device_only):
+                if device_only and spin is not None:
+                    spin(2_000_000)  # the device waits here while the host issues the batch
                 e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                t0 = time.perf_counter()
                 e0.record(stream)
-                issue(group)
-                e1.record(stream)
+                evs = []
+                if group:
+                    vccl.vcclGroupStart()
+                    for k in range(len(specs)):
+                        issue_one(k)
+                    vccl.vcclGroupEnd()
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e1.record(stream)
+                else:
+                    for k in range(len(specs)):
+                        issue_one(k)
+                        ev = torch.cuda.Event(enable_timing=True)
+                        ev.record(stream)
+                        evs.append(ev)
+                    e1 = evs[-1]
                 torch.cuda.synchronize()
-                wall.append(time.perf_counter() - t0)
-                dev.append(e0.elapsed_time(e1) / 1e3)
-            return float(np.median(dev)), float(np.median(wall))
+                total = e0.elapsed_time(e1)
+                if group:
+                    st = np.array(vccl.vcclCommGetLastTimestamps(comms[0], len(specs)), dtype=np.float64)
+                    per = total - (st.max() - st) / 1e6
+                else:
+                    per = np.array([e0.elapsed_time(ev) for ev in evs])
+                return total, per
 
-        def device_only(group):
-            # the launches queued behind a spin kernel (about 3 ms) that keeps
-            # the device busy while the host issues and plans them, so the
-            # events bracket device work only
-            spin = getattr(torch.cuda, "_sleep", None)
-            if spin is None:
+            for group in (0, 1):
+                batch(group, False)  # warm-up (and the output the other path is compared with)
+                if group == 0:
+                    snap = [[x.clone() for x in rr] for rr in recvs]
+                    for rr in recvs:
+                        for x in rr:
+                            x.fill_(0x5A)
+                for device_only in (0, 1):
+                    if device_only and spin is None:
+                        continue
+                    for _ in range(reps):
+                        t, per = batch(group, device_only)
+                        tot[(group, device_only)].append(t)
+                        lat[(group, device_only)].extend(per[small].tolist())
+            lanes = max(lanes, vccl.vcclCommGetLastPlan(comms[0])["nlanes"])
+            same = same and all(bool(torch.equal(a, b)) for ra, rb in zip(snap, recvs) for a, b in zip(ra, rb))
+            err = vccl.vcclCommGetAsyncError(comms[0])
+            if err != vccl.vcclSuccess:
+                raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)} in grouped leg")
+            del recvs, snap
+
+        def med(key):
+            return round(float(np.median(tot[key])), 4) if tot[key] else None
+
+        def pct(key):
+            v = lat[key]
+            if not v:
                 return None
-            dev = []
-            for _ in range(reps):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                spin(2_000_000)
-                e0.record(stream)
-                issue(group)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                dev.append(e0.elapsed_time(e1) / 1e3)
-            return float(np.median(dev))
+            return {"p50_us": round(float(np.percentile(v, 50)) * 1e3, 1),
+                    "p99_us": round(float(np.percentile(v, 99)) * 1e3, 1), "n": len(v)}
 
-        pc_dev, pc_wall = timed(False)
-        pc_only = device_only(False)
-        snap = [[x.clone() for x in rr] for rr in recvs]
-        for rr in recvs:
-            for x in rr:
-                x.fill_(0x5A)
-        g_dev, g_wall = timed(True)
-        g_only = device_only(True)
-        plan = vccl.vcclCommGetLastPlan(comms[0])
-        same = all(bool(torch.equal(a, b)) for ra, rb in zip(snap, recvs) for a, b in zip(ra, rb))
-        err = vccl.vcclCommGetAsyncError(comms[0])
-        if err != vccl.vcclSuccess:
-            raise RuntimeError(f"device error {vccl.vcclGetErrorString(err)} in grouped leg")
-        sizes = [n * ELEM[dt] * (R if c != "allreduce" else 1) for c, dt, n in specs]
-        result[name] = {"ncolls": len(specs), "bytes_total": int(sum(sizes)),
-                        "sub_1MiB_fraction": round(float(np.mean([x < (1 << 20) for x in sizes])), 3),
-                        "grouped_ms": round(g_dev * 1e3, 4), "per_call_ms": round(pc_dev * 1e3, 4),
-                        "grouped_wall_ms": round(g_wall * 1e3, 4), "per_call_wall_ms": round(pc_wall * 1e3, 4),
-                        "speedup": round(pc_dev / g_dev, 3),
-                        "grouped_device_ms": None if g_only is None else round(g_only * 1e3, 4),
-                        "per_call_device_ms": None if pc_only is None else round(pc_only * 1e3, 4),
-                        "device_speedup": None if not (g_only and pc_only) else round(pc_only / g_only, 3),
-                        "lanes": plan["nlanes"],
-                        "grouped_equals_per_call": same}
-        del recvs, snap
+        g, pc, gd, pcd = med((1, 0)), med((0, 0)), med((1, 1)), med((0, 1))
+        result[name] = {"ncolls_per_batch": 64, "bytes_per_batch": int(nbytes / seeds),
+                        "sub_1MiB_fraction": round(nsub / ncoll, 3),
+                        "grouped_ms": g, "per_call_ms": pc, "speedup": round(pc / g, 3),
+                        "grouped_device_ms": gd, "per_call_device_ms": pcd,
+                        "device_speedup": round(pcd / gd, 3) if gd and pcd else None,
+                        "sub_1MiB_latency": {"grouped": pct((1, 0)), "per_call": pct((0, 0)),
+                                             "grouped_device": pct((1, 1)), "per_call_device": pct((0, 1))},
+                        "lanes": lanes, "grouped_equals_per_call": same}
     return result
 
 
-def serving_leg(vccl, torch, si, R, rates, nreq, nwarm, lanes=32, budget=4 << 30):
-    """Poisson request streams through the continuous-batching server."""
+SIZE_BUCKETS = (("under_1MiB", 0, 1 << 20), ("1_to_16MiB", 1 << 20, 16 << 20), ("over_16MiB", 16 << 20, 1 << 62))
+
+
+def _stream_requests(vccl, si, rng, total, R, base_s, base_r, arena, codes, layout):
+    """A request stream of the serving workload: AR 60 % / AG 20 % / RS 20 %,
+    1 KiB..128 MiB log-uniform, dtypes uniform, ragged counts.  layout
+    "random": buffers at random 16-byte aligned offsets of shared arenas
+    (they overlap: timing only); "packed": every request's receive buffers
+    at their own offsets (results can be compared)."""
+    sizes = si.log_uniform_sizes(rng, total, 1 << 10, 128 << 20)
+    reqs, meta, off_r = [], [], 0
+    for i in range(total):
+        u = rng.uniform()
+        coll = "allreduce" if u < 0.6 else ("allgather" if u < 0.8 else "reducescatter")
+        dt = DTYPES[int(rng.integers(0, 3))]
+        E = ELEM[dt]
+        n = max(1, int(sizes[i]) // E // (R if coll != "allreduce" else 1))
+        span_s = n * E * (R if coll == "reducescatter" else 1)
+        span_r = n * E * (R if coll == "allgather" else 1)
+        off_s = int(rng.integers(0, (arena - span_s) // 16 + 1)) * 16
+        if layout == "random":
+            o = int(rng.integers(0, (arena - span_r) // 16 + 1)) * 16
+        else:
+            o = off_r
+            off_r += (span_r + 255) // 256 * 256
+        reqs.append(vccl.make_request(COLL_CODES[coll], codes[dt], vccl.vcclSum, 0, n,
+                                      [b + off_s for b in base_s[dt]], [b + o for b in base_r]))
+        meta.append((coll, dt, n, int(sizes[i]), o, span_r))
+    return reqs, meta, off_r
+
+
+def _bucket_stats(lat_us, sizes):
+    import numpy as np
+    out = {}
+    for name, lo, hi in SIZE_BUCKETS:
+        m = (sizes >= lo) & (sizes < hi)
+        if m.any():
+            out[name] = {"n": int(m.sum()), "p50_us": round(float(np.percentile(lat_us[m], 50)), 1),
+                         "p99_us": round(float(np.percentile(lat_us[m], 99)), 1)}
+    return out
+
+
+def serving_leg(vccl, torch, si, R, rates, nreq, nwarm, lanes=32, budget=4 << 30, check_requests=120):
+    """Poisson request streams through the continuous-batching server and,
+    for the same streams (same requests, same arrival times), through one
+    launch per request (vcclReplayPerCall, native like the server's loop).
+    Per rate: offered vs achieved rate and p50 / p99 latency, overall and per
+    size bucket, for both paths.  Then a check stream with every request's
+    receive buffers apart, served and per-call: the outputs compared bit for
+    bit."""
     import numpy as np
     arena = 128 << 20
     arenas = _send_arenas(torch, si, si.WL_SERVING, R, arena)
@@ -466,45 +536,152 @@ def serving_leg(vccl, torch, si, R, rates, nreq, nwarm, lanes=32, budget=4 << 30
     base_r = [t.data_ptr() for t in recv]
     codes = {"float32": vccl.vcclFloat32, "bfloat16": vccl.vcclBfloat16, "int32": vccl.vcclInt32}
     comms = vccl.vcclCommInitAll(R)
+    stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    srv = vccl.vcclServeCreate(comms, budget, lanes)
     out = {"lanes": lanes, "budget_bytes": budget, "requests_per_rate": nreq, "warmup_per_rate": nwarm,
            "rates": []}
+
+    def summary(lat_ns, arr, sizes):
+        lat = np.asarray(lat_ns[nwarm:], dtype=np.float64) / 1e3
+        done = arr[nwarm:] + lat / 1e6
+        span = float(done.max() - arr[nwarm])
+        return {"achieved_per_s": round(nreq / span, 1), "p50_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_us": round(float(np.percentile(lat, 99)), 1), "by_size": _bucket_stats(lat, sizes[nwarm:])}
+
     try:
         for k, lam in enumerate(rates):
             rng = si.rng_for(si.WL_SERVING, 0, 100 + k)
             total = nreq + nwarm
-            sizes = si.log_uniform_sizes(rng, total, 1 << 10, 128 << 20)
-            reqs, nbytes = [], 0
-            for i in range(total):
-                u = rng.uniform()
-                coll = "allreduce" if u < 0.6 else ("allgather" if u < 0.8 else "reducescatter")
-                dt = DTYPES[int(rng.integers(0, 3))]
-                E = ELEM[dt]
-                n = max(1, int(sizes[i]) // E // (R if coll != "allreduce" else 1))
-                span_s = n * E * (R if coll == "reducescatter" else 1)
-                span_r = n * E * (R if coll == "allgather" else 1)
-                off_s = int(rng.integers(0, (arena - span_s) // 16 + 1)) * 16
-                off_r = int(rng.integers(0, (arena - span_r) // 16 + 1)) * 16
-                reqs.append(vccl.make_request(COLL_CODES[coll], codes[dt], vccl.vcclSum, 0, n,
-                                              [b + off_s for b in base_s[dt]], [b + off_r for b in base_r]))
-                nbytes += int(sizes[i])
+            reqs, meta, _ = _stream_requests(vccl, si, rng, total, R, base_s, base_r, arena, codes, "random")
+            sizes = np.array([m[3] for m in meta])
             arr = si.poisson_arrivals(rng, total, lam)
-            lat, st = vccl.vcclServeReplay(srv, reqs, (arr * 1e9).astype(np.int64))
+            at = (arr * 1e9).astype(np.int64)
+            srv = vccl.vcclServeCreate(comms, budget, lanes)
+            try:
+                lat_s, st = vccl.vcclServeReplay(srv, reqs, at)
+            finally:
+                vccl.vcclServeDestroy(srv)
             if any(x != vccl.vcclSuccess for x in st):
                 raise RuntimeError("serving: a request failed")
-            lat = np.asarray(lat[nwarm:], dtype=np.float64) / 1e3
-            done = arr[nwarm:] + lat / 1e6
-            span = float(done.max() - arr[nwarm])
-            out["rates"].append({"offered_per_s": lam, "achieved_per_s": round(nreq / span, 1),
-                                 "p50_us": round(float(np.percentile(lat, 50)), 1),
-                                 "p99_us": round(float(np.percentile(lat, 99)), 1),
-                                 "mean_bytes": int(nbytes / total)})
+            lat_p, st = vccl.vcclReplayPerCall(comms, reqs, at, stream)
+            if any(x != vccl.vcclSuccess for x in st):
+                raise RuntimeError("per-call replay: a request failed")
+            row = {"offered_per_s": lam, "mean_bytes": int(sizes.mean())}
+            row.update(summary(lat_s, arr, sizes))
+            row["per_call"] = summary(lat_p, arr, sizes)
+            out["rates"].append(row)
+        # bit check: a stream with every request's receive buffers apart
+        rng = si.rng_for(si.WL_SERVING, 0, 99)
+        del recv
+        torch.cuda.empty_cache()
+        probe, meta, need = _stream_requests(vccl, si, rng, check_requests, R, base_s, [0] * R, arena, codes,
+                                             "packed")
+        rbufs = [torch.empty(need, dtype=torch.uint8, device="cuda") for _ in range(R)]
+        reqs = [vccl.make_request(q.coll, q.datatype, q.op, q.root, q.count, list(q.send),
+                                  [rbufs[r].data_ptr() + m[4] for r in range(R)]) for q, m in zip(probe, meta)]
+        arr = (si.poisson_arrivals(rng, check_requests, 5000.0) * 1e9).astype(np.int64)
+        for t in rbufs:
+            t.fill_(0x5A)
+        torch.cuda.synchronize()
+        srv = vccl.vcclServeCreate(comms, budget, lanes)
+        try:
+            _, st = vccl.vcclServeReplay(srv, reqs, arr)
+        finally:
+            vccl.vcclServeDestroy(srv)
+        served = [t.clone() for t in rbufs]
+        for t in rbufs:
+            t.fill_(0x5A)
+        torch.cuda.synchronize()
+        _, st2 = vccl.vcclReplayPerCall(comms, reqs, arr, stream)
+        torch.cuda.synchronize()
+        equal = 0
+        for m in meta:
+            o, span = m[4], m[5]
+            equal += all(bool(torch.equal(served[r][o:o + span], rbufs[r][o:o + span])) for r in range(R))
+        out["served_equals_per_call"] = {"requests": check_requests, "equal": int(equal),
+                                         "arrival_rate_per_s": 5000.0,
+                                         "all_succeeded": all(x == vccl.vcclSuccess for x in st + st2)}
+        del served, rbufs
     finally:
-        vccl.vcclServeDestroy(srv)
         for c in comms:
             vccl.vcclCommDestroy(c)
     return out
+
+
+# The oracle's inputs for the CPU baseline, set before the worker processes
+# fork (and before the GPU is initialised), so every worker holds them.
+_CPU = {}
+
+
+def _cpu_channel(task):
+    """One channel of the ring AllReduce through the oracle's step simulation
+    (channels are independent: the simulation of channel c's slice with one
+    channel is the channel's part of the whole simulation)."""
+    from oracle import simulate as sim
+    c, a, b, chunk_bytes = task
+    out = sim.run("allreduce", [x[a:b] for x in _CPU["xs"]], dtype="float32", nchannels=1, chunk_bytes=chunk_bytes)
+    return c, out[0]
+
+
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline_leg(pool, nworkers, xs, plan, R, S, seconds, gpu_out):
+    """The oracle timed on the host: the step simulation of the same ring
+    AllReduce (inputs, plan) on one thread, then its channels spread over
+    `nworkers` processes; the all-process result is checked element by
+    element against the GPU's output, and so is the oracle's closed-form
+    fold."""
+    import numpy as np
+    from oracle import folds
+    from oracle import partition as pt
+    from oracle import simulate as sim
+    n = len(xs[0])
+    C, chunk = plan["nchannels"], plan["chunkBytes"]
+    exact_fold = bool(np.array_equal(gpu_out.view(np.uint32),
+                                     folds.ring_allreduce(xs, "sum", "float32", C, chunk // 4).view(np.uint32)))
+    reps1, t1, t0 = 0, 0.0, time.perf_counter()
+    while reps1 < 1 or time.perf_counter() - t0 < seconds / 2:
+        a = time.perf_counter()
+        sim.run("allreduce", xs, dtype="float32", nchannels=C, chunk_bytes=chunk)
+        t1 += time.perf_counter() - a
+        reps1 += 1
+    tasks = [(c, a, b, chunk) for c, (a, b) in enumerate(pt.channel_ranges(n, C, pt.align_units("allreduce", 4)))
+             if b > a]
+    repsN, tN, t0 = 0, 0.0, time.perf_counter()
+    got = None
+    while repsN < 1 or time.perf_counter() - t0 < seconds / 2:
+        a = time.perf_counter()
+        parts = dict(pool.map(_cpu_channel, tasks, chunksize=1))
+        tN += time.perf_counter() - a
+        repsN += 1
+        got = parts
+    out = np.concatenate([got[c] for c, _, _, _ in tasks])
+    exact_sim = bool(np.array_equal(out.view(np.uint32), gpu_out.view(np.uint32)))
+    bus = 2 * (R - 1) / R
+    single = S / (t1 / reps1) / 1e9 * bus
+    allc = S / (tN / repsN) / 1e9 * bus
+    info = cpu_info()
+    return {"value": round(allc, 4), "unit": "GB/s", "cores": nworkers, "kind": "oracle",
+            "sample": f"the full workload ({R} ranks x {S >> 20} MiB fp32, the timed launch's plan: {C} channels, "
+                      f"{chunk} B chunks) through the oracle's step simulation (numpy): {repsN} repetitions with "
+                      f"its channels over {nworkers} processes ({tN:.1f} s), {reps1} on one thread ({t1:.1f} s)",
+            "single_thread": {"value": round(single, 4), "unit": "GB/s", "cores": 1},
+            **info,
+            "gpu_result_bit_exact_all_elements": {"step_simulation": exact_sim, "closed_form_fold": exact_fold}}
 
 
 def main():
@@ -533,16 +710,27 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
-    import paper_2507_04786_amd as vccl
     import synthetic_inputs as si
 
     R = args.nranks
     n = args.size_mib * (1 << 20) // 4
     S = n * 4
-    torch.cuda.set_device(0)
     xs = si.rank_inputs(si.WL_RING_AR_SWEEP, R, "float32", n)
+    # the CPU baseline's worker processes fork now, before the GPU is
+    # initialised, each holding the inputs; at most 16 (the host share of one GPU)
+    pool, nworkers = None, 0
+    if not args.no_cpu and not args.profile_pass:
+        import multiprocessing
+        _CPU["xs"] = xs
+        nworkers = max(1, min(16, cpu_info()["usable_cpus"] or 1))
+        pool = multiprocessing.get_context("fork").Pool(nworkers)
+
+    import torch
+
+    import paper_2507_04786_amd as vccl
+
+    torch.cuda.set_device(0)
     sends = [torch.from_numpy(x).cuda() for x in xs]
     recvs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(R)]
     comms = vccl.vcclCommInitAll(R)
@@ -590,6 +778,20 @@ def main():
     # headline: tuner's plan
     wall_step, ev_step = measure(args.steps, args.warmup)
     plan = vccl.vcclCommGetLastPlan(comms[0])
+    # Section V-F's statistic: each of `steps` launches after the warm-up
+    # timed on its own (events on the launch stream), median / min / max
+    per_launch = []
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per_launch.append(e0.elapsed_time(e1))
+    launch_stats = {"runs": len(per_launch), "median_ms": round(float(np.median(per_launch)), 4),
+                    "min_ms": round(float(np.min(per_launch)), 4), "max_ms": round(float(np.max(per_launch)), 4),
+                    "busbw_at_median_gbs": round(S / (float(np.median(per_launch)) / 1e3) / 1e9 * 2 * (R - 1) / R, 2)}
     algbw = S / wall_step / 1e9
     busbw = algbw * 2 * (R - 1) / R
     abytes = alg_bytes_per_launch(plan, R, S)
@@ -616,28 +818,13 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        # the CPU oracle leg: a spot check of the timed launch's result against
-        # the oracle's fold, then the oracle's own timing
-        from oracle import folds
-        from oracle import simulate as sim
-        rng = np.random.default_rng(7)
-        idx = rng.integers(0, n, 4096)
+        # the launch whose result the CPU leg checks: one more of the timed
+        # plan, every element compared
         step()
         torch.cuda.synchronize()
-        got = recvs[0].cpu().numpy()[idx]
-        want = folds.ring_allreduce(xs, "sum", "float32", plan["nchannels"], plan["chunkBytes"] // 4, idx=idx)
-        exact = bool(np.array_equal(got.view(np.uint32), want.view(np.uint32)))
-        reps, t_cpu, t0 = 0, 0.0, time.perf_counter()
-        while reps < 2 or time.perf_counter() - t0 < args.cpu_seconds:
-            t1 = time.perf_counter()
-            sim.run("allreduce", xs, dtype="float32", nchannels=plan["nchannels"], chunk_bytes=plan["chunkBytes"])
-            t_cpu += time.perf_counter() - t1
-            reps += 1
-        per = t_cpu / reps
-        cpu = {"value": round(S / per / 1e9 * 2 * (R - 1) / R, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"the full workload ({R} ranks x {args.size_mib} MiB fp32, same plan), {reps} repetitions, "
-                         f"{t_cpu:.1f} s total, numpy single-threaded",
-               "gpu_result_bit_exact_on_4096_samples": exact}
+        gpu_out = recvs[0].cpu().numpy()
+        cpu = cpu_baseline_leg(pool, nworkers, xs, plan, R, S, args.cpu_seconds, gpu_out)
+        del gpu_out
 
     grouped = None
     if not args.no_grouped:
@@ -672,6 +859,7 @@ def main():
                    "nranks": R, "bytes_per_rank": S, "algo": ["ring", "tree"][plan["algo"]],
                    "proto": ["simple", "ll", "ll128"][plan["proto"]], "nchannels": plan["nchannels"],
                    "chunk_bytes": plan["chunkBytes"], "nthreads": plan["nthreads"], "direct": plan["direct"]},
+        "per_launch": launch_stats,
         "algbw_gbs": round(algbw, 2),
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -688,6 +876,9 @@ def main():
         "serving": serving,
         "cpu_baseline": cpu,
     }
+    if pool is not None:
+        pool.close()
+        pool.join()
     print(json.dumps(out))
 
 

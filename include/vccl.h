@@ -220,6 +220,10 @@ typedef struct {
   int treeRanksPerNode; /* tree topology of the set (VCCL_TREE_RANKS_PER_NODE at init):
                            chains of this many consecutive ranks, double binary tree
                            across the chains; 1 = the plain double binary tree */
+  int ll128;          /* 1: LL128 may be planned on the set's device; 0: LL128 is off
+                         (Section III-C: its tear test found a torn line or did not
+                         finish, or VCCL_LL128=0) and every LL128 plan, tuned or
+                         requested, runs as LL */
 } vcclPlanInfo_t;
 /* Host-side copy; does not synchronise.  All zero before the first launch.
  * vcclInvalidArgument for an unknown handle or a null info. */
@@ -274,6 +278,21 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
  * bound (the counts are then still written); vcclUnhandledHipError if a HIP
  * call failed. */
 vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uint64_t* torn, uint64_t* checked);
+
+/* The planner's choice for one collective, computed on the host with no
+ * device (for tests and tuning studies): `coll` 0 AllReduce .. 4
+ * ReduceScatter, `count` and `datatype` as the per-call API's, `single` 1
+ * for a collective launched alone (a tree may then run as split halves), 0
+ * for one inside a group.  The model device has 256 compute units, the lane
+ * limit vcclCommInitAll gives `nranks` ranks there, the XCD lane map and
+ * store policy, 1024 / nthreads resident workgroups per compute unit, and
+ * LL128 enabled when `ll128` is 1 (0: as after a failed tear test).
+ * `tuning` (may be NULL) overrides the tuner as vcclCommSetTuning does.
+ * Fills *info (caller-owned) as vcclCommGetLastPlan would after that launch.
+ * vcclInvalidArgument for nranks outside 2..16, an unknown coll or datatype,
+ * a zero count, a null info, or a tuning vcclCommSetTuning would refuse. */
+vcclResult_t vcclDebugPlanHost(int nranks, int coll, size_t count, vcclDataType_t datatype, int ll128, int single,
+                               const vcclTuning_t* tuning, vcclPlanInfo_t* info);
 
 /* XCC (accelerator die) id of each of `n` workgroups of a plain launch,
  * written to the host array ids[n] (caller-owned).  Synchronises the device.
@@ -338,6 +357,37 @@ vcclResult_t vcclServeTest(vcclServer_t server, uint64_t id, int* done, vcclResu
  * stay queued and are drained by vcclServeDestroy. */
 vcclResult_t vcclServeReplay(vcclServer_t server, const vcclRequest_t* reqs, const uint64_t* arrival_ns, int n,
                              uint64_t* latency_ns, vcclResult_t* statuses);
+/* The plain per-call path over the same kind of request stream, for
+ * comparison with the server: submits nothing to a server; instead issues
+ * reqs[i] when arrival_ns[i] nanoseconds have passed since the call began
+ * (arrival_ns non-decreasing) as one ordinary per-rank call per rank of the
+ * set (vcclAllReduce ... vcclReduceScatter with comms[r], so each request
+ * is one launch of the per-call planner's plan, on `stream`, a hipStream_t
+ * as void*), and returns when all n launches completed.  latency_ns[i]
+ * receives the host monotonic time at which request i's completion was
+ * observed minus its arrival time; statuses (may be NULL) the call's result,
+ * or the set's asynchronous error after a device-side failure.  comms is the
+ * set's nranks handles in rank order; reqs, arrival_ns, latency_ns and
+ * statuses are caller-owned host arrays of n entries; the request buffers
+ * follow the per-call API's rules.  The set must not be serving.  Errors:
+ * vcclInvalidArgument for a null pointer, n < 0 or handles of another set
+ * or out of order; the first failing call's result otherwise (requests
+ * issued before it have completed when this returns). */
+vcclResult_t vcclReplayPerCall(vcclComm_t* comms, const vcclRequest_t* reqs, const uint64_t* arrival_ns, int n,
+                               void* stream, uint64_t* latency_ns, vcclResult_t* statuses);
+/* The plan request `id` runs with, frozen at submission (it depends only on
+ * the request): algorithm, protocol, channels (= lanes it occupies), chunk,
+ * store policy; nthreads and grid are the persistent kernel's.  A request
+ * whose size (larger per-rank buffer) is at least VCCL_SERVE_FULL_PLAN_BYTES
+ * (default 16 MiB), and every floating-point sum AllReduce (whose bits
+ * depend on the channel count), keeps the per-call plan's channels, up to
+ * the server's lanes; any other request takes at most
+ * VCCL_SERVE_MAX_LANES_PER_REQUEST.  A float sum's bits follow from this
+ * plan exactly as for the same plan launched per call, so with the set's
+ * lane limit as its lanes a server gives every request the per-call bits.  Valid from submission until vcclServeTest reports the
+ * request done.  *info is caller-owned host memory.  vcclInvalidArgument
+ * for a null server or info, or an unknown (or already retired) id. */
+vcclResult_t vcclServeGetPlan(vcclServer_t server, uint64_t id, vcclPlanInfo_t* info);
 /* Monitoring: for each of the first maxEntries (lane, rank) pairs,
  * VCCL_SERVE_DEBUG_WORDS words into out[]: requests posted to the lane (host),
  * the last posted count the workgroup observed (the lane's rank-0 workgroup

@@ -58,7 +58,8 @@ class vcclTuning_t(C.Structure):
 class vcclPlanInfo_t(C.Structure):
     _fields_ = [("algo", C.c_int), ("proto", C.c_int), ("nchannels", C.c_int), ("nthreads", C.c_int),
                 ("direct", C.c_int), ("nlanes", C.c_int), ("nitems", C.c_int), ("ncolls", C.c_int),
-                ("chunkBytes", C.c_size_t), ("grid", C.c_int), ("scope", C.c_int), ("treeRanksPerNode", C.c_int)]
+                ("chunkBytes", C.c_size_t), ("grid", C.c_int), ("scope", C.c_int), ("treeRanksPerNode", C.c_int),
+                ("ll128", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -114,6 +115,10 @@ def _load():
         "vcclServeDestroy": (I, [P]),
         "vcclServeReplay": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64), I, C.POINTER(U64), C.POINTER(I)]),
         "vcclServeDebugState": (I, [P, C.POINTER(U64), I]),
+        "vcclServeGetPlan": (I, [P, U64, C.POINTER(vcclPlanInfo_t)]),
+        "vcclReplayPerCall": (I, [C.POINTER(P), C.POINTER(vcclRequest_t), C.POINTER(U64), I, VP, C.POINTER(U64),
+                                  C.POINTER(I)]),
+        "vcclDebugPlanHost": (I, [I, I, SZ, I, I, I, C.POINTER(vcclTuning_t), C.POINTER(vcclPlanInfo_t)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -123,13 +128,31 @@ def _load():
 
 
 _lib = _load()
+
+# Handles created through this module and not yet destroyed.  At interpreter
+# exit they are destroyed while the HIP runtime is still fully up (Python's
+# exit handlers run before the C runtime's), so no device memory, pinned host
+# memory or event of a communicator set is left to the runtime's own teardown.
+_live: set = set()
+
+
+def _destroy_live():
+    for h in list(_live):
+        _lib.vcclCommDestroy(C.c_void_p(h))
+    _live.clear()
+
+
+import atexit  # noqa: E402
+
+atexit.register(_destroy_live)
 EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy vcclCommAbort "
             "vcclCommGetAsyncError vcclCommCount vcclCommUserRank vcclAllReduce vcclBroadcast vcclReduce "
             "vcclAllGather vcclReduceScatter vcclSend vcclRecv vcclGroupStart vcclGroupEnd vcclCommSetTuning "
             "vcclCommGetLastPlan "
             "vcclCommGetLastTimestamps vcclCommSetTimeout vcclCommDebugSetDeadRanks vcclCommDebugReadFifo "
             "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
-            "vcclServeDestroy vcclServeReplay vcclServeDebugState").split()
+            "vcclServeDestroy vcclServeReplay vcclServeDebugState vcclServeGetPlan vcclDebugPlanHost "
+            "vcclReplayPerCall").split()
 
 
 def lib():
@@ -171,11 +194,13 @@ def vcclCommInitAll(nranks: int, devlist=None) -> list:
     arr = (C.c_void_p * nranks)()
     dl = None if devlist is None else (C.c_int * nranks)(*devlist)
     _check(_lib.vcclCommInitAll(arr, int(nranks), dl), "vcclCommInitAll")
+    _live.update(arr[i] for i in range(nranks))
     return [C.c_void_p(arr[i]) for i in range(nranks)]
 
 
 def vcclCommDestroy(comm):
     _check(_lib.vcclCommDestroy(comm), "vcclCommDestroy")
+    _live.discard(comm.value)
 
 
 def vcclCommAbort(comm):
@@ -340,6 +365,39 @@ def vcclServeDebugState(server, entries: int):
     arr = (C.c_uint64 * (w * entries))()
     _check(_lib.vcclServeDebugState(server, arr, int(entries)), "vcclServeDebugState")
     return [list(arr[w * k:w * k + w]) for k in range(entries)]
+
+
+def vcclReplayPerCall(comms, requests, arrival_ns, stream=None):
+    """The same request stream through one launch per request.
+    Returns (latency_ns list, status list)."""
+    n = len(requests)
+    hs = (C.c_void_p * len(comms))(*[c.value for c in comms])
+    arr = (vcclRequest_t * n)(*requests)
+    at = (C.c_uint64 * n)(*[int(x) for x in arrival_ns])
+    lat = (C.c_uint64 * n)()
+    st = (C.c_int * n)()
+    _check(_lib.vcclReplayPerCall(hs, arr, at, n, _stream(stream), lat, st), "vcclReplayPerCall")
+    return list(lat), list(st)
+
+
+def vcclServeGetPlan(server, rid: int) -> dict:
+    info = vcclPlanInfo_t()
+    _check(_lib.vcclServeGetPlan(server, int(rid), C.byref(info)), "vcclServeGetPlan")
+    return info.as_dict()
+
+
+def vcclDebugPlanHost(nranks, coll, count, datatype, ll128=1, single=1, tuning=None) -> dict:
+    """tuning: None or a dict of vcclCommSetTuning's keyword arguments."""
+    info = vcclPlanInfo_t()
+    t = None
+    if tuning is not None:
+        d = dict(algo=-1, proto=-1, nchannels=0, nthreads=0, chunkBytes=0, direct=-1)
+        d.update(tuning)
+        t = C.byref(vcclTuning_t(int(d["algo"]), int(d["proto"]), int(d["nchannels"]), int(d["nthreads"]),
+                                 int(d["chunkBytes"]), int(d["direct"])))
+    _check(_lib.vcclDebugPlanHost(int(nranks), int(coll), int(count), int(datatype), int(ll128), int(single), t,
+                                  C.byref(info)), "vcclDebugPlanHost")
+    return info.as_dict()
 
 
 def vcclServeDestroy(server):

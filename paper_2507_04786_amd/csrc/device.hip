@@ -1307,9 +1307,16 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
 
 // ------------------------------------------------------------------ serving kernel
 // Persistent: every (lane, rank) workgroup waits for its lane's next posted
-// entry, runs it like any work item, and publishes completion.  Exits on the
-// stop word (raised by the host, or by the first workgroup that waited
-// `idleTicks` without work), the abort word, or a failed wait.
+// entry, runs it like any work item, and publishes completion.  The lane's
+// leader (rank 0) alone decides when the lane stops taking work: on the
+// host's stop word, on the idle word (raised by the first leader that waited
+// `idleTicks` without work: a lane whose workgroups left could not run what
+// the host posts next, so the whole grid ends together and the host
+// relaunches it), or on an abort or a failed wait; it then stores the exit
+// marker into the lane's release counter.  The lane's other workgroups leave
+// only on that marker, the host's stop word (raised once every request has
+// completed) or a failure, so an entry the leader accepted always finds its
+// whole lane.
 
 __device__ __forceinline__ uint64_t ldSystem64(const uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1357,6 +1364,7 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
           __hip_atomic_store(dbg, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
           __hip_atomic_store(dbg + 2, (uint64_t)it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
+        if (!leader && (p & SERVE_EXIT)) break;  // the leader closed the lane
         if (p > seq) {
           cmd = 1;
           break;
@@ -1368,18 +1376,20 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
           if (ldSystem32(d.stop)) break;
           // an abort, or a failed wait anywhere (timeout): the whole grid leaves
           if (ldSystem32(d.comm->abortFlag) || ldSystem32(d.comm->errorWord)) break;
-          if (leader && nowTicks() - t0 > d.idleTicks) {
-            // the whole kernel stops together (a lane whose workgroups left
-            // could not run the work the host posts next); the host relaunches
-            // it when work arrives
-            __hip_atomic_store(d.stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            break;
+          if (leader) {
+            if (ldSystem32(d.idle)) break;
+            if (nowTicks() - t0 > d.idleTicks) {
+              __hip_atomic_store(d.idle, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+              break;
+            }
           }
         }
       }
       if (cmd) {
         __hip_atomic_store(dbg + 1, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         __hip_atomic_store(dbg + 3, nowTicks(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      } else if (leader) {
+        stAgent(laneSeq, SERVE_EXIT | seq);  // release the lane's other workgroups for good
       }
       sCmd = cmd;
     }

@@ -222,7 +222,81 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
   info.grid = grid;
   info.scope = plans[0].scope;
   info.treeRanksPerNode = c->ranksPerNode;
+  info.ll128 = c->ll128 ? 1 : 0;
   return vcclSuccess;
+}
+
+// LL128 tear test (Section III-C: LL128 is used only where 128-byte stores
+// are never observed split).  `pairs` writer/reader workgroup pairs exchange
+// `lines` lines for `rounds` rounds under the store policy `scope`; every
+// wait is bounded by maxUs.  Allocates and frees its own buffers on every
+// path.
+hipError_t tearProbe(int device, int pairs, int lines, int rounds, int scope, uint64_t maxUs, uint64_t* torn,
+                     uint64_t* checked, bool* timedOut) {
+  char* bufs = nullptr;
+  uint64_t* acks = nullptr;
+  unsigned long long* counts = nullptr;
+  uint32_t* failed = nullptr;
+  const size_t bytes = (size_t)pairs * lines * LL128_LINE;
+  const size_t ackBytes = (size_t)pairs * 32 * sizeof(uint64_t);
+  hipError_t e = hipMalloc((void**)&bufs, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&acks, ackBytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&counts, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&failed, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(bufs, 0, bytes);
+  if (e == hipSuccess) e = hipMemset(acks, 0, ackBytes);
+  if (e == hipSuccess) e = hipMemset(counts, 0, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(failed, 0, sizeof(uint32_t));
+  int wallKHz = 100000;
+  if (hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, device) != hipSuccess || wallKHz <= 0)
+    wallKHz = 100000;
+  const uint64_t maxTicks = (uint64_t)wallKHz * maxUs / 1000ull;
+  if (e == hipSuccess) e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, scope, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  unsigned long long h[2] = {0, 0};
+  uint32_t hf = 0;
+  if (e == hipSuccess) e = hipMemcpy(h, counts, sizeof(h), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&hf, failed, sizeof(hf), hipMemcpyDeviceToHost);
+  if (bufs) hipFree(bufs);
+  if (acks) hipFree(acks);
+  if (counts) hipFree(counts);
+  if (failed) hipFree(failed);
+  *torn = h[0];
+  *checked = h[1];
+  *timedOut = hf != 0;
+  return e;
+}
+
+// Whether LL128 may be planned on `device`: VCCL_LL128=0 turns it off and
+// VCCL_LL128=1 on without a test; otherwise the tear test runs once per
+// device and process, under both store policies (XCD scope: writer and
+// reader on one XCD; device scope: on different XCDs), each wait bounded by
+// 100 ms.  Any torn line, a wait past its bound or a failed HIP call turns
+// LL128 off for every set on that device.
+bool ll128Allowed(int device) {
+  static int8_t state[64] = {0};  // 0 untested, 1 allowed, 2 off
+  const std::string env = envStr("VCCL_LL128");
+  if (env == "0") return false;
+  if (env == "1") return true;
+  if (device < 0 || device >= 64) return false;
+  if (state[device] == 0) {
+    bool ok = true;
+    const int cfg[2][2] = {{SCOPE_XCD, 16}, {SCOPE_DEVICE, 4}};
+    for (const auto& pc : cfg) {
+      uint64_t torn = 0, checked = 0;
+      bool timedOut = false;
+      hipError_t e = tearProbe(device, pc[1], 2048, 6, pc[0], 100000, &torn, &checked, &timedOut);
+      if (e != hipSuccess || timedOut || torn != 0 || checked == 0) {
+        logInfo("LL128 off: tear test (scope %d) %s, %llu torn of %llu lines", pc[0],
+                e != hipSuccess ? hipGetErrorString(e) : (timedOut ? "timed out" : "ran"),
+                (unsigned long long)torn, (unsigned long long)checked);
+        ok = false;
+        break;
+      }
+    }
+    state[device] = ok ? 1 : 2;
+  }
+  return state[device] == 1;
 }
 
 }  // namespace vccl
@@ -570,6 +644,65 @@ vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int p
   return vcclSuccess;
 }
 
+vcclResult_t vcclDebugPlanHost(int nranks, int coll, size_t count, vcclDataType_t datatype, int ll128, int single,
+                               const vcclTuning_t* tuning, vcclPlanInfo_t* info) {
+  if (!info || nranks < 2 || nranks > VCCL_MAX_RANKS || coll < COLL_ALLREDUCE || coll > COLL_REDUCESCATTER ||
+      datatype < vcclInt32 || datatype > vcclBfloat16 || count == 0)
+    return vcclInvalidArgument;
+  // the model device: nothing here reaches the HIP runtime (every occupancy
+  // the planner may ask for is filled in)
+  Clique c;
+  c.nranks = nranks;
+  c.numCUs = 256;
+  c.maxLanes = std::max(32, std::min(MAX_LANES, (c.numCUs / nranks) / 8 * 8));
+  for (int i = 1; i <= 16; ++i) c.occupancy[i] = std::max(1, 16 / i);
+  c.host.scope = SCOPE_XCD;
+  c.host.slotBytes[PROTO_SIMPLE] = SLOT_BYTES_SIMPLE;
+  c.host.slotBytes[PROTO_LL] = SLOT_BYTES_LL;
+  c.host.slotBytes[PROTO_LL128] = SLOT_BYTES_LL128;
+  c.deviceScopeBytes = 16 << 20;
+  c.ll128 = ll128 != 0;
+  buildTrees(nranks, 1, c.host.parent, c.host.child, c.host.childIdx, c.host.nchild);
+  if (tuning) {
+    const vcclTuning_t* t = tuning;
+    if (t->algo < -1 || t->algo > 1 || t->proto < -1 || t->proto > 2 || t->nchannels < 0 ||
+        t->nchannels > c.maxLanes || (t->nthreads != 0 && (t->nthreads < 64 || t->nthreads > 1024 || t->nthreads % 64)) ||
+        t->chunkBytes % 16)
+      return vcclInvalidArgument;
+    c.apiTune.algo = t->algo;
+    c.apiTune.proto = t->proto;
+    c.apiTune.nchannels = t->nchannels;
+    c.apiTune.nthreads = t->nthreads;
+    c.apiTune.chunkBytes = t->chunkBytes;
+    c.apiTune.direct = t->direct;
+  }
+  Coll x{};
+  x.coll = (uint8_t)coll;
+  x.dtype = (int)datatype;
+  x.op = vcclSum;
+  x.count = count;
+  Plan p;
+  vcclResult_t r = planColl(&c, x, &p, single != 0);
+  if (r != vcclSuccess) return r;
+  const int nlanes = p.split ? 8 * ((p.nchannels + 7) / 8) + p.nchannels : p.nchannels;
+  vcclPlanInfo_t o{};
+  o.algo = p.algo;
+  o.proto = p.proto;
+  o.nchannels = p.nchannels;
+  o.nthreads = p.nthreads;
+  o.direct = p.direct;
+  o.nlanes = nlanes;
+  o.nitems = nlanes;
+  o.ncolls = 1;
+  o.chunkBytes = (size_t)p.chunkBytes;
+  o.grid = 8 * nranks * ((nlanes + 7) / 8);
+  o.scope = p.scope;
+  o.treeRanksPerNode = 1;
+  o.ll128 = c.ll128 ? 1 : 0;
+  *info = o;
+  return vcclSuccess;
+}
+
 vcclResult_t vcclProbeXccIds(int n, int* ids) {
   if (n <= 0 || !ids) return vcclInvalidArgument;
   int* d = nullptr;
@@ -590,42 +723,15 @@ vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uin
     return vcclInvalidArgument;
   if (scope != SCOPE_DEVICE && scope != SCOPE_XCD) return vcclInvalidArgument;
   if (scope == SCOPE_XCD && pairs % 8) return vcclInvalidArgument;  // plain stores: each pair on one XCD
-  char* bufs = nullptr;
-  uint64_t* acks = nullptr;
-  unsigned long long* counts = nullptr;
-  uint32_t* failed = nullptr;
-  const size_t bytes = (size_t)pairs * lines * LL128_LINE;
-  const size_t ackBytes = (size_t)pairs * 32 * sizeof(uint64_t);
-  // every buffer is freed on every path below
-  hipError_t e = hipMalloc((void**)&bufs, bytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&acks, ackBytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&counts, 2 * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc((void**)&failed, sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMemset(bufs, 0, bytes);
-  if (e == hipSuccess) e = hipMemset(acks, 0, ackBytes);
-  if (e == hipSuccess) e = hipMemset(counts, 0, 2 * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMemset(failed, 0, sizeof(uint32_t));
-  int dev = 0, wallKHz = 100000;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&wallKHz, hipDeviceAttributeWallClockRate, dev);
-  const uint64_t maxTicks = (uint64_t)wallKHz * 1000ull * 5ull;  // 5 s per wait
-  if (e == hipSuccess) e = vcclLaunchTearProbe(bufs, acks, pairs, lines, rounds, counts, maxTicks, failed, scope, nullptr);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  unsigned long long h[2] = {0, 0};
-  uint32_t hf = 0;
-  if (e == hipSuccess) e = hipMemcpy(h, counts, sizeof(h), hipMemcpyDeviceToHost);
-  if (e == hipSuccess) e = hipMemcpy(&hf, failed, sizeof(hf), hipMemcpyDeviceToHost);
-  if (bufs) hipFree(bufs);
-  if (acks) hipFree(acks);
-  if (counts) hipFree(counts);
-  if (failed) hipFree(failed);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return vcclUnhandledHipError;
+  bool timedOut = false;
+  hipError_t e = tearProbe(dev, pairs, lines, rounds, scope, 5000000, torn, checked, &timedOut);
   if (e != hipSuccess) {
     logError("tear probe", e, __FILE__, __LINE__);
     return vcclUnhandledHipError;
   }
-  *torn = h[0];
-  *checked = h[1];
-  return hf ? vcclRemoteError : vcclSuccess;
+  return timedOut ? vcclRemoteError : vcclSuccess;
 }
 
 }  // extern "C"

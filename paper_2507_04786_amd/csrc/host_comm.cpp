@@ -249,12 +249,14 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   // take device scope from the same size.
   c->deviceScopeBytes = (uint64_t)envLong("VCCL_DEVICE_SCOPE_BYTES", 16 << 20);
   c->treeSplit = envLong("VCCL_TREE_SPLIT", 1) != 0;
+  // Section III-C: LL128 only where its 128-byte lines are never seen torn
+  c->ll128 = ll128Allowed(device);
   if (c->xcdMap && envStr("VCCL_SCOPE") != "device") {
     c->host.scope = SCOPE_XCD;
     e = hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(e, "hipMemcpy(devcomm)");
   }
-  logInfo("traffic scope %s", c->host.scope == SCOPE_XCD ? "xcd" : "device");
+  logInfo("traffic scope %s, LL128 %s", c->host.scope == SCOPE_XCD ? "xcd" : "device", c->ll128 ? "on" : "off");
   *out = c;
   return vcclSuccess;
 }

@@ -112,6 +112,7 @@ struct Clique {
   uint64_t deviceScopeBytes = 0;  // Simple AllGathers and Send/Recv copies this large use device scope
   bool treeSplit = true;          // split Simple tree channels into concurrent halves
   int ranksPerNode = 1;           // tree topology: chains of this many ranks, trees across them
+  bool ll128 = true;              // LL128 may be planned (its tear test passed on this device)
   uint64_t* claim = nullptr;  // per-XCD role counters (device)
   uint64_t claimBase = 0;     // role claims of all launches so far, per XCD
 };
@@ -141,6 +142,9 @@ double estimateCost(const Clique* c, const WorkItem& w);
 
 // host_api.cpp
 vcclResult_t launchColls(Clique* c, const std::vector<Coll>& colls);
+hipError_t tearProbe(int device, int pairs, int lines, int rounds, int scope, uint64_t maxUs, uint64_t* torn,
+                     uint64_t* checked, bool* timedOut);
+bool ll128Allowed(int device);
 
 // env helpers
 std::string envStr(const char* name);

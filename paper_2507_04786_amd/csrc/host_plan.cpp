@@ -34,11 +34,14 @@ static uint64_t unitsOf(uint8_t coll, size_t count, int dtype) {
   return copyOnly(coll) ? (uint64_t)count * dtypeBytes(dtype) : (uint64_t)count;
 }
 
-// Largest chunk one slot can carry per protocol (slot payload).
+// Largest chunk one slot can carry per protocol (slot payload): the whole
+// slot under Simple, half of it under LL (4 data bytes per 8-byte unit),
+// 120 of every 128 bytes under LL128.
 static uint64_t maxChunkBytes(const Clique* c, int proto) {
-  if (proto == PROTO_SIMPLE) return c->host.slotBytes[PROTO_SIMPLE];
-  if (proto == PROTO_LL) return SLOT_BYTES_LL / 2;
-  return (uint64_t)(SLOT_BYTES_LL128 / LL128_LINE) * LL128_DATA;
+  const uint64_t slot = c->host.slotBytes[proto];
+  if (proto == PROTO_SIMPLE) return slot;
+  if (proto == PROTO_LL) return slot / 2;
+  return slot / LL128_LINE * LL128_DATA;
 }
 
 // Measured plan table: for each (ranks, collective, log2 of the per-rank
@@ -134,6 +137,10 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   int algo = pick(c->apiTune.algo, c->envTune.algo, dfltAlgo);
   if (algo == ALGO_TREE && coll.coll != COLL_ALLREDUCE) algo = ALGO_RING;
   int proto = pick(c->apiTune.proto, c->envTune.proto, dfltProto);
+  // Section III-C: where LL128's lines are not guaranteed whole (the tear
+  // test failed, or VCCL_LL128=0) every LL128 plan, chosen or requested,
+  // becomes LL, the other flag protocol
+  if (proto == PROTO_LL128 && !c->ll128) proto = PROTO_LL;
   // --- channels: up to two workgroups per CU (while one waits on a flag the
   // other moves data)
   const int laneCap = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));

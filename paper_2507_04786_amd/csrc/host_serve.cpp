@@ -49,6 +49,7 @@ struct vcclServer {
   int block = 512;
   size_t budget = 0, used = 0;
   int maxLanesPerReq = 1;
+  uint64_t fullPlanBytes = 0;
   uint64_t bypassNs = 0;
   hipStream_t stream = nullptr;
   ServeDesc desc{};
@@ -93,9 +94,25 @@ uint64_t laneDone(vcclServer* s, int lane) {
   return m;
 }
 
+// Host words the persistent kernel polls: the stop word (host) and, 128 bytes
+// further, the idle word (raised by the kernel).
+constexpr int kIdleWord = 32;
+
+bool kernelLeaving(vcclServer* s) {
+  return __atomic_load_n(s->hStop, __ATOMIC_ACQUIRE) != 0 || __atomic_load_n(s->hStop + kIdleWord, __ATOMIC_ACQUIRE) != 0;
+}
+
 vcclResult_t launchKernel(vcclServer* s) {
   for (int l = 0; l < s->L; ++l) s->desc.startSeq[l] = laneDone(s, l);
   __atomic_store_n(s->hStop, 0u, __ATOMIC_RELEASE);
+  __atomic_store_n(s->hStop + kIdleWord, 0u, __ATOMIC_RELEASE);
+  // the release counters restart from zero: the previous kernel (same stream)
+  // has ended, and the exit markers its leaders left must not reach this one
+  hipError_t me = hipMemsetAsync(s->dLaneSeq, 0, sizeof(uint64_t) * SERVE_STRIDE_U64 * s->L, s->stream);
+  if (me != hipSuccess) {
+    logError("hipMemsetAsync(laneSeq)", me, __FILE__, __LINE__);
+    return vcclUnhandledHipError;
+  }
   s->desc.perXcd = (uint32_t)(s->c->nranks * ((s->L + 7) / 8));
   s->desc.claimBase = s->c->claimBase;
   hipError_t e = vcclLaunchServe(s->desc, s->grid, s->block, s->stream);
@@ -201,10 +218,11 @@ vcclResult_t progress(vcclServer* s) {
     admitted = true;
   }
   // the kernel leaves after an idle period; bring it back when work is pending
-  // (the kernel only ends after raising the stop word, so the runtime is
-  // asked only then)
-  if (s->running && __atomic_load_n(s->hStop, __ATOMIC_ACQUIRE) != 0 && hipStreamQuery(s->stream) == hipSuccess)
-    s->running = false;
+  // (the kernel only ends after the stop or idle word was raised, so the
+  // runtime is asked only then).  Entries posted to lanes whose leader had
+  // already left are run by the relaunched kernel: it starts every lane at
+  // the lane's completed count.
+  if (s->running && kernelLeaving(s) && hipStreamQuery(s->stream) == hipSuccess) s->running = false;
   if (!s->running && (admitted || !s->inflight.empty())) return launchKernel(s);
   return vcclSuccess;
 }
@@ -233,6 +251,7 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   // device more efficiently and let two large requests overlap)
   s->maxLanesPerReq = (int)std::max(1L, std::min<long>(lanes, envLong("VCCL_SERVE_MAX_LANES_PER_REQUEST",
                                                                       std::max(1, lanes / 2))));
+  s->fullPlanBytes = (uint64_t)envLong("VCCL_SERVE_FULL_PLAN_BYTES", 16 << 20);
   s->bypassNs = (uint64_t)envLong("VCCL_SERVE_BYPASS_US", 500) * 1000ull;
   int occ = 0;
   if (vcclServeOccupancy(s->block, &occ) != hipSuccess || occ < 1) {
@@ -265,12 +284,13 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   memset(s->hQueue, 0, sizeof(ServeEntry) * lanes * SERVE_QUEUE);
   memset(s->hPosted, 0, sizeof(uint64_t) * SERVE_STRIDE_U64 * MAX_LANES);
   memset(s->hDone, 0, sizeof(uint64_t) * SERVE_STRIDE_U64 * MAX_LANES * MAX_RANKS);
-  *s->hStop = 0;
+  memset(s->hStop, 0, 256);
   s->desc.comm = c->dcomm;
   s->desc.queue = s->hQueue;
   s->desc.posted = s->hPosted;
   s->desc.done = s->hDone;
   s->desc.stop = s->hStop;
+  s->desc.idle = s->hStop + kIdleWord;
   memset(s->hDbg, 0, sizeof(uint64_t) * SERVE_STRIDE_U64 * MAX_LANES * MAX_RANKS);
   s->desc.dbg = s->hDbg;
   s->desc.mirror = s->dMirror;
@@ -324,8 +344,18 @@ vcclResult_t vcclServeSubmit(vcclServer_t s, const vcclRequest_t* req, uint64_t*
   // at most half the lanes, unless the request holds more than half the
   // budget: then nothing of its size can run beside it and it takes the
   // lanes its plan asks for
+  // A request keeps its per-call plan's channels (up to the server's lanes)
+  // when it is at least fullPlanBytes large, so it is served as fast as the
+  // same call launched alone, or when it is a floating-point sum
+  // AllReduce, the one collective whose bits depend on the channel count
+  // (the ring's segments and the tree's per-channel trees follow it), so it
+  // gives the per-call bits.  Every other request takes at most
+  // maxLanesPerReq lanes, so that several overlap; their results do not
+  // depend on the channel count.  The cap depends only on the request.
   const Plan full = q->plan;
-  q->plan.nchannels = std::min(full.nchannels, s->maxLanesPerReq);
+  const bool large = collSizeBytes((uint8_t)req->coll, req->count, req->datatype, R) >= s->fullPlanBytes;
+  const bool channelBits = req->coll == COLL_ALLREDUCE && req->op == vcclSum && req->datatype != vcclInt32;
+  q->plan.nchannels = std::min(full.nchannels, (large || channelBits) ? s->L : s->maxLanesPerReq);
   q->bytes = requestBytes(c, *req, q->plan);
   if (q->bytes > s->budget / 2) {
     q->plan.nchannels = std::min(full.nchannels, s->L);
@@ -395,6 +425,113 @@ vcclResult_t vcclServeReplay(vcclServer_t s, const vcclRequest_t* reqs, const ui
     }
   }
   return vcclSuccess;
+}
+
+vcclResult_t vcclServeGetPlan(vcclServer_t s, uint64_t id, vcclPlanInfo_t* info) {
+  if (!s || !info) return vcclInvalidArgument;
+  auto it = s->reqs.find(id);
+  if (it == s->reqs.end()) return vcclInvalidArgument;
+  const Req* q = it->second;
+  const Plan& p = q->plan;
+  vcclPlanInfo_t o{};
+  o.algo = p.algo;
+  o.proto = p.proto;
+  o.nchannels = p.nchannels;
+  o.nthreads = s->block;
+  o.direct = p.direct;
+  o.nlanes = p.nchannels;
+  o.nitems = p.nchannels;
+  o.ncolls = 1;
+  o.chunkBytes = (size_t)p.chunkBytes;
+  o.grid = s->grid;
+  o.scope = p.scope;
+  o.treeRanksPerNode = s->c->ranksPerNode;
+  o.ll128 = s->c->ll128 ? 1 : 0;
+  *info = o;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclReplayPerCall(vcclComm_t* comms, const vcclRequest_t* reqs, const uint64_t* arrival_ns, int n,
+                               void* stream, uint64_t* latency_ns, vcclResult_t* statuses) {
+  if (!comms || !comms[0] || !reqs || !arrival_ns || !latency_ns || n < 0) return vcclInvalidArgument;
+  Clique* c = cliqueOf(comms[0]);
+  if (!c) return vcclInvalidArgument;
+  const int R = c->nranks;
+  for (int r = 0; r < R; ++r)
+    if (!comms[r] || cliqueOf(comms[r]) != c || rankOf(comms[r]) != r) return vcclInvalidArgument;
+  hipStream_t st = (hipStream_t)stream;
+  VCCL_HIPCHECK(hipSetDevice(c->device));
+  // one event per request in flight, reused round robin; the stream runs the
+  // launches in issue order, so they complete in that order
+  constexpr int kEvents = 256;
+  std::vector<hipEvent_t> ev(kEvents, nullptr);
+  vcclResult_t result = vcclSuccess;
+  for (auto& e : ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) result = vcclUnhandledHipError;
+  std::vector<uint64_t> tArr(n, 0);
+  int next = 0, finished = 0;
+  const uint64_t t0 = nowNs();
+  auto retire = [&](bool block) {
+    while (finished < next) {
+      hipEvent_t e = ev[finished % kEvents];
+      hipError_t q = block ? hipEventSynchronize(e) : hipEventQuery(e);
+      if (q == hipErrorNotReady) return;
+      if (q != hipSuccess) result = vcclUnhandledHipError;
+      latency_ns[finished] = nowNs() - tArr[finished];
+      ++finished;
+      block = false;
+    }
+  };
+  while (result == vcclSuccess && finished < n) {
+    const uint64_t now = nowNs();
+    while (result == vcclSuccess && next < n && now - t0 >= arrival_ns[next]) {
+      if (next - finished >= kEvents) retire(true);  // every event is in flight: wait for the oldest
+      const vcclRequest_t& q = reqs[next];
+      tArr[next] = t0 + arrival_ns[next];
+      vcclResult_t r = vcclSuccess;
+      for (int k = 0; k < R && r == vcclSuccess; ++k) {
+        const void* sb = q.send[k];
+        void* rb = q.recv[k];
+        switch (q.coll) {
+          case COLL_ALLREDUCE:
+            r = vcclAllReduce(sb, rb, q.count, (vcclDataType_t)q.datatype, (vcclRedOp_t)q.op, comms[k], st);
+            break;
+          case COLL_BROADCAST:
+            r = vcclBroadcast(sb, rb, q.count, (vcclDataType_t)q.datatype, q.root, comms[k], st);
+            break;
+          case COLL_REDUCE:
+            r = vcclReduce(sb, rb, q.count, (vcclDataType_t)q.datatype, (vcclRedOp_t)q.op, q.root, comms[k], st);
+            break;
+          case COLL_ALLGATHER:
+            r = vcclAllGather(sb, rb, q.count, (vcclDataType_t)q.datatype, comms[k], st);
+            break;
+          case COLL_REDUCESCATTER:
+            r = vcclReduceScatter(sb, rb, q.count, (vcclDataType_t)q.datatype, (vcclRedOp_t)q.op, comms[k], st);
+            break;
+          default:
+            r = vcclInvalidArgument;
+        }
+      }
+      if (statuses) statuses[next] = r;
+      if (r != vcclSuccess) {
+        result = r;
+        break;
+      }
+      if (hipEventRecord(ev[next % kEvents], st) != hipSuccess) result = vcclUnhandledHipError;
+      ++next;
+    }
+    retire(false);
+  }
+  if (result != vcclSuccess) hipStreamSynchronize(st);
+  for (auto e : ev)
+    if (e) hipEventDestroy(e);
+  if (result == vcclSuccess && statuses) {
+    vcclResult_t a = vcclSuccess;
+    vcclCommGetAsyncError(comms[0], &a);
+    if (a != vcclSuccess)
+      for (int i = 0; i < n; ++i) statuses[i] = a;
+  }
+  return result;
 }
 
 // Debug view: for every (lane, rank): posted (host), last posted value the

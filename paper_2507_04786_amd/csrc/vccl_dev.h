@@ -123,6 +123,13 @@ struct LaunchDesc {
 // Every workgroup of the lane runs the entry and then publishes its own
 // `done` counter (with a system-scope release, so the outputs are visible to
 // later work).
+// Only the leader decides when its lane stops taking work: it leaves on the
+// host's stop word, on the idle word (raised by any leader that waited
+// idleTicks without work), or on a failure, and then stores SERVE_EXIT into
+// the lane's release counter.  The other workgroups of the lane leave only
+// on that marker, the host's stop word or a failure, so an entry the leader
+// accepted is always run by the whole lane.
+constexpr uint64_t SERVE_EXIT = 1ull << 63;
 constexpr int SERVE_QUEUE = 4;
 constexpr int SERVE_STRIDE_U64 = 16;  // counters 128 B apart
 constexpr int SERVE_DBG_WORDS = 5;    // per (lane, rank): seen, picked, polls, pickup tick, finish tick
@@ -138,9 +145,11 @@ struct ServeDesc {
   uint64_t* posted;         // [nlanes] * SERVE_STRIDE_U64
   uint64_t* done;           // [nlanes * nranks] * SERVE_STRIDE_U64
   uint32_t* stop;           // set by the host to end the kernel
+  uint32_t* idle;           // set by the first leader that waited idleTicks without work
   uint64_t* dbg;            // per (lane, rank): SERVE_DBG_WORDS words, SERVE_STRIDE_U64 apart
   ServeEntry* mirror;       // device memory: [nlanes][SERVE_QUEUE] copies made by the leaders
   uint64_t* laneSeq;        // device memory: [nlanes] * SERVE_STRIDE_U64, entries released
+                            // (zeroed before every launch), or SERVE_EXIT | seq
   uint64_t idleTicks;       // the kernel exits after this long without work
   uint32_t nlanes, nranks, xcdMap, perXcd;
   uint64_t claimBase;

@@ -2,7 +2,11 @@
  * (include/vccl.h) and the HIP runtime's C API: R virtual ranks on the
  * current device.
  *
- *   c_client [R [n]]
+ *   c_client [R [n [keep]]]
+ *
+ * With "keep" the program exits without destroying its communicators or
+ * freeing its buffers, leaving the set's device memory, pinned host words
+ * and events to process exit.
  *
  * Checks, on int32 data whose results are exact in any summation order:
  *   - AllReduce sum: recv_r[i] = sum over ranks q of x_q[i];
@@ -74,6 +78,7 @@ static void expectEqual(const char* what, const int32_t* got, const int32_t* wan
 int main(int argc, char** argv) {
   const int R = argc > 1 ? atoi(argv[1]) : 4;
   const size_t n = argc > 2 ? (size_t)strtoull(argv[2], NULL, 10) : 100003;
+  const int keep = argc > 3 && strcmp(argv[3], "keep") == 0;
   if (R < 2 || R > MAXR || n == 0) {
     fprintf(stderr, "usage: c_client [R in 2..%d [n > 0]]\n", MAXR);
     return 1;
@@ -176,6 +181,8 @@ int main(int argc, char** argv) {
          "\"allreduce_8B_issue_us_p50\": %.1f}\n",
          failures == 0, R, n, rt[REPS / 2], issue[REPS / 2]);
 
+  fflush(stdout);
+  if (keep) return failures == 0 ? 0 : 4;
   for (int q = 0; q < R; ++q) {
     HIP_OK(hipFree(send[q]));
     HIP_OK(hipFree(recv[q]));

@@ -31,3 +31,14 @@ def test_c_client(client, R, n):
     rec = json.loads(line)
     assert rec["ok"] == 1 and rec["nranks"] == R and rec["count"] == n
     print(line, flush=True)
+
+
+def test_exit_with_live_sets_is_clean(client):
+    """The same program leaves its communicator set and buffers alive and
+    returns from main: the process still exits with status 0 (the library
+    runs no code of its own at exit, so nothing of it touches the HIP
+    runtime while the runtime tears down)."""
+    res = subprocess.run([client, "8", "4099", "keep"], capture_output=True, text=True, timeout=90)
+    assert res.returncode == 0, f"exit {res.returncode}\n{res.stdout}\n{res.stderr}"
+    rec = json.loads([l for l in res.stdout.splitlines() if l.startswith("{")][-1])
+    assert rec["ok"] == 1

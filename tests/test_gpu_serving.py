@@ -48,9 +48,16 @@ def _buffers(reqs):
     return bufs
 
 
-def _submit(vccl, srv, req, buf):
+def _submit(vccl, srv, req, buf, plans=None, k=None):
+    """Submits one request; with `plans`, records the plan it was admitted
+    with under key k and checks it equals any plan recorded before (a
+    request's plan depends only on the request)."""
     coll, dtype, n, _ = req
-    return vccl.vcclServeSubmit(srv, CODES[coll], vccl.DTYPE_NAMES[dtype], vccl.vcclSum, 0, n, buf[0], buf[1])
+    rid = vccl.vcclServeSubmit(srv, CODES[coll], vccl.DTYPE_NAMES[dtype], vccl.vcclSum, 0, n, buf[0], buf[1])
+    if plans is not None:
+        p = vccl.vcclServeGetPlan(srv, rid)
+        assert plans.setdefault(k, p) == p, (k, plans[k], p)
+    return rid
 
 
 def _wait(vccl, srv, ids):
@@ -78,16 +85,17 @@ def test_alone_equals_mix_and_oracle(vccl):
         srv = vccl.vcclServeCreate(comms, 4 << 30, 16)
         try:
             alone = []
+            plans = {}
             # no device-wide synchronisation while the persistent kernel runs
             # (it would wait for the kernel's idle exit): completion is
             # published with a system-scope release, so plain copies suffice
-            for req, buf in zip(reqs, bufs):
-                _wait(vccl, srv, [_submit(vccl, srv, req, buf)])
+            for k, (req, buf) in enumerate(zip(reqs, bufs)):
+                _wait(vccl, srv, [_submit(vccl, srv, req, buf, plans, k)])
                 alone.append([H.from_dev(r, req[1]).copy() for r in buf[1]])
                 for r in buf[1]:
                     r.view(H.torch().uint8).fill_(0x5A)
                 H.torch().cuda.current_stream().synchronize()
-            ids = [_submit(vccl, srv, req, buf) for req, buf in zip(reqs, bufs)]
+            ids = [_submit(vccl, srv, req, buf, plans, k) for k, (req, buf) in enumerate(zip(reqs, bufs))]
             _wait(vccl, srv, ids)
             mix = _snapshot(bufs, reqs)
         finally:
@@ -96,21 +104,22 @@ def test_alone_equals_mix_and_oracle(vccl):
         for k, (coll, dtype, n, xs) in enumerate(reqs):
             for r in range(R):
                 assert np.array_equal(alone[k][r].view(np.uint8), mix[k][r].view(np.uint8)), (k, coll, dtype, n, r)
+            plan = plans[k]
             if coll == "allgather":
                 want = defs.allgather(xs)
             elif dtype == "int32":
                 want = (defs.allreduce if coll == "allreduce" else defs.reducescatter)(xs, "sum", "int32")
             elif coll == "reducescatter":
                 want = [folds.ring_reducescatter(xs, "sum", dtype, r) for r in range(R)]
+            elif plan["algo"] == vccl.vcclAlgoTree:
+                # float AllReduce: the oracle's fold for the plan it was served with
+                want = [folds.tree_allreduce(xs, "sum", dtype, plan["nchannels"])] * R
             else:
-                want = None
-            if want is not None:
-                for r in range(R):
-                    assert np.array_equal(mix[k][r].view(np.uint8), want[r].view(np.uint8)), (k, coll, dtype, r)
-            else:
-                # float AllReduce: every rank identical, within the fp64 bound
-                for r in range(1, R):
-                    assert np.array_equal(mix[k][r].view(np.uint8), mix[k][0].view(np.uint8))
+                want = [folds.ring_allreduce(xs, "sum", dtype, plan["nchannels"],
+                                             plan["chunkBytes"] // H.ELEM[dtype])] * R
+            for r in range(R):
+                assert np.array_equal(mix[k][r].view(np.uint8), want[r].view(np.uint8)), (k, coll, dtype, r, plan)
+            if coll == "allreduce" and dtype != "int32":
                 err = np.abs(H_to64(dtype, mix[k][0]) - defs.fp64_sum(xs, dtype))
                 assert (err <= defs.sum_error_bound(xs, dtype) * (1 + 1e-9) + 1e-30).all()
         # after the server the per-call path works again on the same lanes
@@ -270,5 +279,55 @@ def test_every_collective_in_place_max_and_errors(vccl):
                         assert np.array_equal(served[k][r], want[r]), (k, coll, op, r)
         assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
     finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
+
+
+def test_requests_across_idle_exits(vccl):
+    """The persistent kernel leaves after 1 ms without work and is relaunched
+    when work arrives.  Bursts of 1-4 requests (1-4 lanes each) separated by
+    0-3 ms pauses post work while leaders are leaving, so entries land on
+    lanes whose leader has already closed them as well as on lanes still
+    open.  Every request must complete with the definition's result; the
+    500 ms wait limit turns a lane left without its workgroups into a quick
+    RemoteError rather than a long wait."""
+    import os
+    import time
+    Rs = 4
+    old = os.environ.get("VCCL_SERVE_IDLE_US")
+    os.environ["VCCL_SERVE_IDLE_US"] = "1000"
+    comms = vccl.vcclCommInitAll(Rs)
+    try:
+        vccl.vcclCommSetTimeout(comms[0], 500000)
+        rng = np.random.default_rng(2024)
+        pool = []
+        for k in range(4):
+            n = int(rng.integers(256, 64 * 1024))
+            xs = si.rank_inputs(si.WL_SERVING, Rs, "int32", n, lo=-2**20, hi=2**20, extra=555000 + k)
+            pool.append((n, xs, [H.to_dev(x) for x in xs], [H.empty_dev(n, "int32") for _ in range(Rs)],
+                         defs.allreduce(xs, "sum", "int32")[0]))
+        H.torch().cuda.synchronize()
+        srv = vccl.vcclServeCreate(comms, 1 << 30, 8)
+        try:
+            for burst in range(60):
+                ks = rng.permutation(4)[:int(rng.integers(1, 5))]
+                ids = [vccl.vcclServeSubmit(srv, 0, vccl.vcclInt32, vccl.vcclSum, 0, pool[k][0], pool[k][2],
+                                            pool[k][3]) for k in ks]
+                _wait(vccl, srv, ids)
+                for k in ks:
+                    n, xs, _, recvs, want = pool[k]
+                    for r in range(Rs):
+                        assert np.array_equal(H.from_dev(recvs[r], "int32"), want), (burst, k, r)
+                        recvs[r].view(H.torch().uint8).fill_(0x5A)
+                H.torch().cuda.current_stream().synchronize()
+                time.sleep(float(rng.uniform(0, 3e-3)))
+        finally:
+            vccl.vcclServeDestroy(srv)
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+    finally:
+        if old is None:
+            del os.environ["VCCL_SERVE_IDLE_US"]
+        else:
+            os.environ["VCCL_SERVE_IDLE_US"] = old
         for c in comms:
             vccl.vcclCommDestroy(c)
