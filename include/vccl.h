@@ -237,6 +237,37 @@ vcclResult_t vcclCommGetLastPlan(vcclComm_t comm, vcclPlanInfo_t* info);
  * pointer. */
 vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int n, int* written);
 
+/* ---------------------------------------------------------------- allocation-free AllReduce */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the ring
+ * AllReduce of vcclAllReduce for `nranks` (2..16) virtual ranks, with no
+ * communicator set and no allocation.  sendbuffs[r] / recvbuffs[r] (host
+ * arrays of nranks device pointers, caller-owned, element-aligned; in place
+ * when equal) are rank r's buffers of `count` elements; recv[r][i] = op over
+ * ranks of send[q][i].  `stream` is a hipStream_t as void*; plan (may be
+ * NULL, caller-owned host memory) receives the plan that ran.
+ * Everything beyond the caller's buffers lives in one file-scope device
+ * array of 40.25 MiB per device (the descriptor, the counters of at most 128
+ * lanes x ranks, 8 Simple slots of 32 KiB and 8 LL slots of 8 KiB per
+ * connection): channels are limited to min(32, 128 / nranks), Simple chunks
+ * to 32 KiB, LL chunks to 4 KiB; the protocol is Simple or LL, never LL128,
+ * and the algorithm the ring, so results are the oracle's ring fold for the
+ * reported plan.  The first call on a device looks the array up with that
+ * device current; every call then enqueues two launches on `stream` (one
+ * that rewrites the descriptor and zeroes the counters and LL slots it
+ * uses, then the collective), and calls nothing that allocates.  All calls
+ * on one device share its array: calls that overlap on that device (other
+ * streams, other threads) race and must not be made.  Every wait is bounded
+ * (5 s); a wait that runs out leaves the output undefined and is not
+ * reported here (there is no communicator to query), and the next call
+ * starts afresh.  Errors: vcclInvalidArgument for a null array or buffer
+ * (count > 0), nranks outside 2..16, an unknown datatype or op, a
+ * misaligned buffer or count above 2^40; vcclUnhandledHipError when a HIP
+ * call fails; vcclSuccess with nothing enqueued for count == 0. */
+vcclResult_t vcclAllReduceNoAlloc(const void* const* sendbuffs, void* const* recvbuffs, int nranks, size_t count,
+                                  vcclDataType_t datatype, vcclRedOp_t op, void* stream, vcclPlanInfo_t* plan);
+
 /* ---------------------------------------------------------------- failure handling
  * Every wait on the device is bounded: after `timeout_us` microseconds without
  * progress the waiting workgroup records vcclRemoteError and exits.  Applies

@@ -116,6 +116,7 @@ def _load():
         "vcclServeReplay": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64), I, C.POINTER(U64), C.POINTER(I)]),
         "vcclServeDebugState": (I, [P, C.POINTER(U64), I]),
         "vcclServeGetPlan": (I, [P, U64, C.POINTER(vcclPlanInfo_t)]),
+        "vcclAllReduceNoAlloc": (I, [C.POINTER(VP), C.POINTER(VP), I, SZ, I, I, VP, C.POINTER(vcclPlanInfo_t)]),
         "vcclReplayPerCall": (I, [C.POINTER(P), C.POINTER(vcclRequest_t), C.POINTER(U64), I, VP, C.POINTER(U64),
                                   C.POINTER(I)]),
         "vcclDebugPlanHost": (I, [I, I, SZ, I, I, I, C.POINTER(vcclTuning_t), C.POINTER(vcclPlanInfo_t)]),
@@ -152,7 +153,7 @@ EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy v
             "vcclCommGetLastTimestamps vcclCommSetTimeout vcclCommDebugSetDeadRanks vcclCommDebugReadFifo "
             "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
             "vcclServeDestroy vcclServeReplay vcclServeDebugState vcclServeGetPlan vcclDebugPlanHost "
-            "vcclReplayPerCall").split()
+            "vcclReplayPerCall vcclAllReduceNoAlloc").split()
 
 
 def lib():
@@ -228,6 +229,17 @@ def vcclCommUserRank(comm) -> int:
 def vcclAllReduce(send, recv, count, datatype, op, comm, stream=None):
     _check(_lib.vcclAllReduce(_ptr(send), _ptr(recv), int(count), int(datatype), int(op), comm, _stream(stream)),
            "vcclAllReduce")
+
+
+def vcclAllReduceNoAlloc(sends, recvs, count, datatype, op, stream=None) -> dict:
+    """sends / recvs: one buffer per rank.  Returns the plan that ran."""
+    R = len(sends)
+    sa = (C.c_void_p * R)(*[_ptr(x) for x in sends])
+    ra = (C.c_void_p * R)(*[_ptr(x) for x in recvs])
+    info = vcclPlanInfo_t()
+    _check(_lib.vcclAllReduceNoAlloc(sa, ra, R, int(count), int(datatype), int(op), _stream(stream),
+                                     C.byref(info)), "vcclAllReduceNoAlloc")
+    return info.as_dict()
 
 
 def vcclBroadcast(send, recv, count, datatype, root, comm, stream=None):

@@ -22,7 +22,7 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libvccl.so")
 
-SOURCES = ["device.hip", "host_comm.cpp", "host_plan.cpp", "host_api.cpp", "host_serve.cpp"]
+SOURCES = ["device.hip", "host_comm.cpp", "host_plan.cpp", "host_api.cpp", "host_serve.cpp", "host_noalloc.cpp"]
 HEADERS = ["vccl_dev.h", "host_internal.h", "tune_table.inc"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

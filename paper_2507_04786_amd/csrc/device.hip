@@ -1542,6 +1542,31 @@ __global__ void __launch_bounds__(256) tearProbeKernel(char* bufs, uint64_t* ack
   if (threadIdx.x == 0 && sFail) atomicOr(failed, 1u);
 }
 
+// ------------------------------------------------------------------ allocation-free AllReduce
+// The scratch of vcclAllReduceNoAlloc (layout in vccl_dev.h).  Each device the
+// library runs on holds its own copy until the process ends.
+static __device__ __align__(256) char scratch[NA_SCRATCH_BYTES];
+
+// Before each allocation-free launch, on the same stream: writes the DevComm
+// the collective runs with, and zeroes [NA_OFF_WORDS, NA_OFF_CTR + ctrBytes)
+// (abort and error words, claim counters, the counters the launch uses) and
+// the first llBytes of the LL FIFOs.  The host checks ctrBytes <= NA_CTR_BYTES
+// and llBytes <= the LL region.
+__global__ void __launch_bounds__(256) noAllocPrepKernel(char* base, const DevComm comm, uint64_t ctrBytes,
+                                                           uint64_t llBytes) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nthr = (uint64_t)gridDim.x * blockDim.x;
+  const u32x4 zero = {0, 0, 0, 0};
+  u32x4* r1 = (u32x4*)(base + NA_OFF_WORDS);
+  const uint64_t n1 = (NA_OFF_CTR - NA_OFF_WORDS + ctrBytes) / 16;
+  for (uint64_t i = tid; i < n1; i += nthr) r1[i] = zero;
+  u32x4* r2 = (u32x4*)(base + NA_OFF_FIFO_LL);
+  const uint64_t n2 = llBytes / 16;
+  for (uint64_t i = tid; i < n2; i += nthr) r2[i] = zero;
+  if (blockIdx.x == 0 && threadIdx.x < sizeof(DevComm) / 8)
+    ((uint64_t*)(base + NA_OFF_COMM))[threadIdx.x] = ((const uint64_t*)&comm)[threadIdx.x];
+}
+
 }  // namespace vccl
 
 // ------------------------------------------------------------------ host-side launchers
@@ -1565,6 +1590,33 @@ hipError_t vcclLaunchServe(const vccl::ServeDesc& d, int grid, int block, hipStr
 
 hipError_t vcclServeOccupancy(int block, int* blocksPerCU) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocksPerCU, (const void*)vccl::serveKernel, block, 0);
+}
+
+// Device address of the allocation-free scratch on `device` (the current
+// device): looked up once per device with that device current and kept; the
+// array's name in host code is only a stand-in for the symbol, never an
+// address to hand to a kernel or a copy.
+hipError_t vcclScratchPtr(int device, char** ptr) {
+  static char* ptrs[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  if (!ptrs[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(vccl::scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptrs[device] = (char*)p;
+  }
+  *ptr = ptrs[device];
+  return hipSuccess;
+}
+
+hipError_t vcclLaunchNoAllocPrep(char* base, const vccl::DevComm& comm, uint64_t ctrBytes, uint64_t llBytes,
+                                 hipStream_t stream) {
+  if (ctrBytes > vccl::NA_CTR_BYTES || llBytes > vccl::NA_CONNS * vccl::NSLOTS * vccl::NA_SLOT_LL || ctrBytes % 16 ||
+      llBytes % 16)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(vccl::noAllocPrepKernel, dim3(64), dim3(256), 0, stream, base, comm, ctrBytes, llBytes);
+  return hipGetLastError();
 }
 
 hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream) {

@@ -18,6 +18,9 @@ hipError_t vcclCollOccupancy(int block, int* blocksPerCU);
 hipError_t vcclLaunchXccProbe(int* dIds, int n, hipStream_t stream);
 hipError_t vcclLaunchServe(const vccl::ServeDesc& d, int grid, int block, hipStream_t stream);
 hipError_t vcclServeOccupancy(int block, int* blocksPerCU);
+hipError_t vcclScratchPtr(int device, char** ptr);
+hipError_t vcclLaunchNoAllocPrep(char* base, const vccl::DevComm& comm, uint64_t ctrBytes, uint64_t llBytes,
+                                 hipStream_t stream);
 hipError_t vcclLaunchTearProbe(char* bufs, uint64_t* acks, int pairs, int lines, int rounds,
                                unsigned long long* counts, uint64_t maxTicks, uint32_t* failed, int scope,
                                hipStream_t stream);

@@ -156,4 +156,30 @@ struct ServeDesc {
   uint64_t startSeq[MAX_LANES];
 };
 
+// ---------------------------------------------------------------- allocation-free AllReduce
+// vcclAllReduceNoAlloc keeps everything it needs beyond the caller's buffers
+// in one file-scope device array (device.hip), laid out as below: the
+// DevComm it runs with, the abort and error words, the per-XCD claim
+// counters, the counters of up to NA_CONNS ring connections (lanes x ranks)
+// and their FIFOs, Simple slots of NA_SLOT_SIMPLE bytes and LL slots of
+// NA_SLOT_LL bytes.  Every call rewrites the DevComm and zeroes the words,
+// the claim counters, the counters it uses and, under LL, the LL slots it
+// uses, so each call starts from step 0 whatever ran before.
+constexpr uint64_t NA_CONNS = 128;
+constexpr uint64_t NA_MAX_LANES = 32;
+constexpr uint64_t NA_SLOT_SIMPLE = 32u * 1024u;
+constexpr uint64_t NA_SLOT_LL = 8u * 1024u;
+constexpr uint64_t NA_OFF_COMM = 0;
+constexpr uint64_t NA_OFF_WORDS = 1024;  // abort word at +0, error word at +128
+constexpr uint64_t NA_OFF_CLAIM = 2048;  // 8 counters, CLAIM_STRIDE_U64 apart
+constexpr uint64_t NA_OFF_CTR = 4096;
+constexpr uint64_t NA_CTR_BYTES = NA_CONNS * NCONN * CTR_RECORD_U64 * 8;
+constexpr uint64_t NA_OFF_FIFO_SIMPLE = 256u * 1024u;
+constexpr uint64_t NA_OFF_FIFO_LL = NA_OFF_FIFO_SIMPLE + NA_CONNS * NSLOTS * NA_SLOT_SIMPLE;
+constexpr uint64_t NA_SCRATCH_BYTES = NA_OFF_FIFO_LL + NA_CONNS * NSLOTS * NA_SLOT_LL;
+static_assert(sizeof(DevComm) <= NA_OFF_WORDS - NA_OFF_COMM, "DevComm fits its scratch slot");
+static_assert(NA_OFF_CLAIM + 8 * CLAIM_STRIDE_U64 * 8 <= NA_OFF_CTR, "claim counters fit");
+static_assert(NA_OFF_CTR + NA_CTR_BYTES <= NA_OFF_FIFO_SIMPLE, "counters fit before the FIFOs");
+static_assert(NA_MAX_LANES <= MAX_INLINE, "one inline work item per lane");
+
 }  // namespace vccl
