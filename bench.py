@@ -199,12 +199,55 @@ def collectives_leg(vccl, torch, si, R=16, size=64 << 20, steps=10):
             out[name] = {"ms": round(t * 1e3, 4), "busbw_gbs": round(size / t / 1e9 * bus[coll], 2),
                          "hbm_frac": round(ab / t / 1e9 / HBM_PEAK_GBS, 4),
                          "algo": ["ring", "tree"][plan["algo"]], "proto": ["simple", "ll", "ll128"][plan["proto"]],
-                         "nchannels": plan["nchannels"], "direct": plan["direct"]}
+                         "nchannels": plan["nchannels"], "nthreads": plan["nthreads"],
+                         "chunk_bytes": plan["chunkBytes"], "direct": plan["direct"]}
+            if name in ("allreduce", "allreduce_tree"):
+                out[name]["roles"] = role_profile(vccl, torch, comms, issue, plan)
     finally:
         vccl.vcclCommSetTuning(comms[0])
         for c in comms:
             vccl.vcclCommDestroy(c)
     return out
+
+
+def role_profile(vccl, torch, comms, issue, plan):
+    """One more launch of `issue` with per-workgroup profiling on: for every
+    (lane, rank) its span and the part spent waiting for step counters.
+    Grouped by role -- for a tree, the rank's place in its channel's tree
+    (leaf, interior, root) and, for a split channel, the half (up / down);
+    for a ring, one group -- with the median busy fraction (1 - wait / span)
+    and the median span of each group."""
+    import numpy as np
+    R = len(comms)
+    vccl.vcclCommDebugProfile(comms[0], True)
+    try:
+        issue()
+        torch.cuda.synchronize()
+        recs = vccl.vcclCommDebugReadProfile(comms[0], 64 * R)
+    finally:
+        vccl.vcclCommDebugProfile(comms[0], False)
+    C = plan["nchannels"]
+    split = plan["algo"] == 1 and plan["nlanes"] > C
+    off = 8 * ((C + 7) // 8)
+    parents = [vccl.vcclCommGetTree(comms[0], t) for t in (0, 1)] if plan["algo"] == 1 else None
+    groups = {}
+    for k, (t0, t1, wait, items) in enumerate(recs):
+        if not items:
+            continue
+        lane, rank = divmod(k, R)
+        if parents is None:
+            key = "ring"
+        else:
+            ch = lane if lane < C else lane - off
+            par = parents[ch % 2]
+            nk = sum(1 for q in range(R) if par[q] == rank)
+            role = "root" if par[rank] < 0 else ("leaf" if nk == 0 else "interior")
+            key = (("up_" if lane < C else "down_") if split else "") + role
+        span = max(1, t1 - t0)
+        groups.setdefault(key, []).append((1.0 - wait / span, span))
+    return {k: {"workgroups": len(v), "busy_frac_median": round(float(np.median([b for b, _ in v])), 3),
+                "span_us_median": round(float(np.median([sp for _, sp in v])) / 1e3, 1)}
+            for k, v in sorted(groups.items())}
 
 
 def alltoall_leg(vccl, torch, si, R=8, size=64 << 20, steps=10):

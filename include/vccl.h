@@ -89,7 +89,9 @@ vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist);
 
 /* Section II-A: ncclCommDestroy completes pending operations, then frees.
  * Destroying any rank's handle waits for all work of the set and frees the
- * set's resources once every rank's handle has been destroyed. */
+ * set's resources once every rank's handle has been destroyed.  Destroy every
+ * set before the process exits: the library runs no code at exit, so a set
+ * left alive is released by the HIP runtime's own teardown. */
 vcclResult_t vcclCommDestroy(vcclComm_t comm);
 
 /* Section II-A: ncclCommAbort terminates at once and cancels ongoing
@@ -282,13 +284,31 @@ vcclResult_t vcclCommSetTimeout(vcclComm_t comm, uint64_t timeout_us);
  * Synchronises the device.  vcclInvalidArgument for an unknown handle. */
 vcclResult_t vcclCommDebugSetDeadRanks(vcclComm_t comm, uint32_t mask);
 
+/* Test and tuning hook: with enable != 0, every later launch of the set
+ * records, for each of its workgroups, when it started and ended, how long
+ * it waited for step counters (Simple's head and tail, LL / LL128 send
+ * credits; the workgroup's thread 0 in its waits) and how many work items it
+ * ran; enable == 0 stops recording.  Synchronises the device; the first
+ * enable allocates the records (64 lanes x nranks x 4 words).
+ * vcclInvalidArgument for an unknown handle; vcclUnhandledHipError if the
+ * allocation fails. */
+vcclResult_t vcclCommDebugProfile(vcclComm_t comm, int enable);
+/* The records of the set's most recent launch (recorded when profiling was
+ * on), one per (lane, rank) in lane-major order, lanes 0 .. nlanes-1 of that
+ * launch: out[4k .. 4k+3] = start, end and waiting time in ns of the device
+ * wall clock, items run (all zero for a workgroup that ran nothing).  Waits
+ * for that launch.  out is a caller-owned host array of 4 * maxEntries words;
+ * *written receives the entries written (0 when nothing was recorded).
+ * vcclInvalidArgument for an unknown handle or a null pointer. */
+vcclResult_t vcclCommDebugReadProfile(vcclComm_t comm, uint64_t* out, int maxEntries, int* written);
+
 /* Copies `bytes` bytes of the FIFO of connection (channel, receiving rank,
  * connection 0 = ring) for protocol `proto` starting at byte `offset` into the
  * host buffer `dst` (caller-owned).  Synchronises the device.  For
  * line-format checks.  vcclInvalidArgument for an unknown handle, a null
  * dst, channel outside [0, lane limit), rank outside [0, nranks), proto
  * outside 0..2, or a range that runs past the connection's FIFO
- * (8 slots of 512 KiB Simple (VCCL_SIMPLE_SLOT_BYTES), 32 KiB LL or
+ * (8 slots of 256 KiB Simple (VCCL_SIMPLE_SLOT_BYTES), 32 KiB LL or
  * 600 KiB LL128). */
 vcclResult_t vcclCommDebugReadFifo(vcclComm_t comm, int channel, int rank, int proto, size_t offset, void* dst,
                                    size_t bytes);
@@ -324,6 +344,13 @@ vcclResult_t vcclProbeLL128Tear(int pairs, int lines, int rounds, int scope, uin
  * a zero count, a null info, or a tuning vcclCommSetTuning would refuse. */
 vcclResult_t vcclDebugPlanHost(int nranks, int coll, size_t count, vcclDataType_t datatype, int ll128, int single,
                                const vcclTuning_t* tuning, vcclPlanInfo_t* info);
+
+/* The set's double binary tree `tree` (0 or 1; Section II-C): parents[r]
+ * receives rank r's parent, -1 for the root.  Channel c of a tree AllReduce
+ * runs on tree c mod 2.  parents is a caller-owned host array of nranks
+ * entries.  vcclInvalidArgument for an unknown handle, a null array or a
+ * tree other than 0 or 1. */
+vcclResult_t vcclCommGetTree(vcclComm_t comm, int tree, int* parents);
 
 /* XCC (accelerator die) id of each of `n` workgroups of a plain launch,
  * written to the host array ids[n] (caller-owned).  Synchronises the device.

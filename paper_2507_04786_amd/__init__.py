@@ -17,7 +17,9 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libvccl.so")
+# VCCL_LIB may name another build of the same library (the race-detection
+# build, lib/libvccl_jitter.so); the default is the in-tree libvccl.so
+LIB_PATH = os.environ.get("VCCL_LIB") or os.path.join(_HERE, "lib", "libvccl.so")
 
 # ---------------------------------------------------------------- constants (vccl.h)
 vcclSuccess = 0
@@ -116,6 +118,9 @@ def _load():
         "vcclServeReplay": (I, [P, C.POINTER(vcclRequest_t), C.POINTER(U64), I, C.POINTER(U64), C.POINTER(I)]),
         "vcclServeDebugState": (I, [P, C.POINTER(U64), I]),
         "vcclServeGetPlan": (I, [P, U64, C.POINTER(vcclPlanInfo_t)]),
+        "vcclCommDebugProfile": (I, [P, I]),
+        "vcclCommGetTree": (I, [P, I, C.POINTER(I)]),
+        "vcclCommDebugReadProfile": (I, [P, C.POINTER(U64), I, C.POINTER(I)]),
         "vcclAllReduceNoAlloc": (I, [C.POINTER(VP), C.POINTER(VP), I, SZ, I, I, VP, C.POINTER(vcclPlanInfo_t)]),
         "vcclReplayPerCall": (I, [C.POINTER(P), C.POINTER(vcclRequest_t), C.POINTER(U64), I, VP, C.POINTER(U64),
                                   C.POINTER(I)]),
@@ -153,7 +158,8 @@ EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy v
             "vcclCommGetLastTimestamps vcclCommSetTimeout vcclCommDebugSetDeadRanks vcclCommDebugReadFifo "
             "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
             "vcclServeDestroy vcclServeReplay vcclServeDebugState vcclServeGetPlan vcclDebugPlanHost "
-            "vcclReplayPerCall vcclAllReduceNoAlloc").split()
+            "vcclReplayPerCall vcclAllReduceNoAlloc vcclCommDebugProfile vcclCommDebugReadProfile "
+            "vcclCommGetTree").split()
 
 
 def lib():
@@ -294,6 +300,26 @@ def vcclCommGetLastTimestamps(comm, n: int) -> list:
     w = C.c_int()
     _check(_lib.vcclCommGetLastTimestamps(comm, arr, int(n), C.byref(w)), "vcclCommGetLastTimestamps")
     return [arr[i] for i in range(w.value)]
+
+
+def vcclCommDebugProfile(comm, enable: bool = True):
+    _check(_lib.vcclCommDebugProfile(comm, int(bool(enable))), "vcclCommDebugProfile")
+
+
+def vcclCommDebugReadProfile(comm, entries: int) -> list:
+    """Per (lane, rank) of the last launch: [start_ns, end_ns, wait_ns, items]."""
+    arr = (C.c_uint64 * (4 * entries))()
+    w = C.c_int()
+    _check(_lib.vcclCommDebugReadProfile(comm, arr, int(entries), C.byref(w)), "vcclCommDebugReadProfile")
+    return [list(arr[4 * k:4 * k + 4]) for k in range(w.value)]
+
+
+def vcclCommGetTree(comm, tree: int) -> list:
+    """Parent of every rank in the set's tree `tree` (0 or 1), -1 at the root."""
+    n = vcclCommCount(comm)
+    arr = (C.c_int * n)()
+    _check(_lib.vcclCommGetTree(comm, int(tree), arr), "vcclCommGetTree")
+    return list(arr)
 
 
 def vcclCommSetTimeout(comm, timeout_us: int):

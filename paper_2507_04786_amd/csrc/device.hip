@@ -58,6 +58,31 @@ __device__ __forceinline__ void orSystem32(uint32_t* p, uint32_t v) {
 __device__ __forceinline__ void drainVmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 __device__ __forceinline__ uint64_t nowTicks() { return __builtin_amdgcn_s_memrealtime(); }
 
+// Race-detection build (compiled with -DVCCL_JITTER, never the default):
+// every publish -- a counter store, a batch of LL / LL128 line stores -- is
+// preceded by a pause of a random 0..63 x 512 clocks, so that producers and
+// consumers meet in orders the normal timing rarely gives, and every FIFO
+// slot a receiver has consumed is overwritten with a poison pattern (and,
+// under LL / LL128, a flag that is never current) before its credit is
+// returned, so that a read of a slot before its data was published, or
+// after its credit was returned, gives wrong results instead of stale
+// right ones.
+#ifdef VCCL_JITTER
+constexpr bool kJitter = true;
+__device__ __forceinline__ void jitterPause() {
+  uint32_t h = (uint32_t)nowTicks() * 0x9E3779B1u ^ (uint32_t)(threadIdx.x >> 6) * 0x85EBCA77u ^
+               (uint32_t)blockIdx.x * 0xC2B2AE3Du;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 13;
+  for (uint32_t k = __builtin_amdgcn_readfirstlane(h & 63u); k; --k) __builtin_amdgcn_s_sleep(8);
+}
+#else
+constexpr bool kJitter = false;
+__device__ __forceinline__ void jitterPause() {}
+#endif
+constexpr uint32_t POISON = 0xDEADBEEFu;
+
 // Workgroup-uniform values (stream bases, sizes, strides) often reach the
 // code that uses them through LDS, memory or a call, where the compiler can
 // no longer tell they are uniform: it keeps them in vector registers and
@@ -240,7 +265,8 @@ struct Ctx {
   int rank, lane, nranks;
   int tid, nthreads, wave, nwaves, lid;
   int* sAbort;  // LDS flag: set when any wait of this workgroup failed
-  uint32_t slotB;   // FIFO slot bytes of the running item's protocol
+  uint32_t slotB;   // FIFO slot bytes of the running item's connections (ring or tree) and protocol
+  uint64_t* sWait;  // LDS: ticks this workgroup spent in counter waits (profiling launches only), or null
 };
 
 // LDS words through LDS pointers: LDS instructions wait only on LDS, where a
@@ -266,6 +292,7 @@ __device__ __forceinline__ Ctx uniformCtx(const Ctx& c0) {
   c.lid = c0.lid;
   c.sAbort = uniformPtr(c0.sAbort);
   c.slotB = uniform(c0.slotB);
+  c.sWait = uniformPtr(c0.sWait);
   return c;
 }
 __device__ __forceinline__ WorkItem uniformItem(const WorkItem& w0) {
@@ -312,6 +339,7 @@ __device__ __forceinline__ bool waitCounter(const Ctx& c, const uint64_t* ctr, u
 template <int SC>
 __device__ __forceinline__ bool syncConns(const Ctx& c, Conn* r, int rmask, Conn* s, int smask) {
   if (c.tid == 0) {
+    const uint64_t t0 = c.sWait ? nowTicks() : 0;
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -320,6 +348,7 @@ __device__ __forceinline__ bool syncConns(const Ctx& c, Conn* r, int rmask, Conn
     for (int i = 0; i < 3; ++i)
       if (ok && (rmask & (1 << i))) ok = waitCounter<SC>(c, r[i].tail, r[i].step + 1);
     if (!ok) *abortWord(c) = 1;
+    if (c.sWait) *(LdsU64*)c.sWait += nowTicks() - t0;
   }
   __syncthreads();
   return !*abortWord(c);
@@ -507,6 +536,23 @@ __device__ bool stepSimple(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
 
   drainVmem();
   __syncthreads();
+  if constexpr (kJitter) {
+    // every wave has read the received slots: poison them before their
+    // credit goes back
+    if (!a.recvDirect) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (!(a.rmask & (1 << i))) continue;
+        const __amdgpu_buffer_rsrc_t rs = makeRsrc(r[i].fifo + (r[i].step % NSLOTS) * slotB, (uint32_t)slotB);
+        for (uint32_t off = (uint32_t)c.tid * 16; off < a.nbytes; off += (uint32_t)c.nthreads * 16)
+          __builtin_amdgcn_raw_buffer_store_b128(u32x4{POISON, POISON, POISON, POISON}, rs, off, 0,
+                                                 StoreAux<SC>::value);
+      }
+      drainVmem();
+      __syncthreads();
+    }
+    if (c.tid == 0) jitterPause();
+  }
   if (c.tid == 0) {
     // every wave drained its stores before the barrier: the chunk is
     // visible at the traffic's scope before the tail that announces it
@@ -539,9 +585,31 @@ __device__ __forceinline__ bool waitCredits(const Ctx& c, Conn* s, int smask) {
 // every wave has read the received slot (its loads returned: their values
 // were used) before the head store frees it.
 template <int SC>
-__device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, int rmask, int smask) {
+__device__ __forceinline__ bool finishFlagStep(const Ctx& c, Conn* r, Conn* s, int rmask, int smask,
+                                               uint32_t consumedBytes = 0, bool ll128 = false) {
   __syncthreads();
   bool ok = !*abortWord(c);
+  if constexpr (kJitter) {
+    // poison the consumed lines: payload POISON, flag 0 (never current: the
+    // first flag of a connection is 1); LL units are 8 bytes (data, flag),
+    // LL128 lines carry their flag in bytes 120..127
+    if (ok && rmask) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (!(rmask & (1 << i))) continue;
+        const __amdgpu_buffer_rsrc_t rs = makeRsrc(r[i].fifo + (r[i].step % NSLOTS) * (uint64_t)c.slotB, c.slotB);
+        for (uint32_t off = (uint32_t)c.tid * 16; off < consumedBytes; off += (uint32_t)c.nthreads * 16) {
+          const bool flagWords = ll128 ? ((off / 16) % 8 == 7) : false;
+          const u32x4 v = ll128 ? (flagWords ? u32x4{POISON, POISON, 0u, 0u} : u32x4{POISON, POISON, POISON, POISON})
+                                : u32x4{POISON, 0u, POISON, 0u};
+          __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, StoreAux<SC>::value);
+        }
+      }
+      drainVmem();
+      __syncthreads();
+    }
+    if (c.tid == 0) jitterPause();
+  }
   if (c.tid == 0 && ok) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -651,6 +719,7 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
       }
     }
     if (!alive) break;
+    if constexpr (kJitter) jitterPause();  // a wave's line stores of this pass
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (valid[u] == 0) continue;
@@ -670,7 +739,7 @@ __device__ bool stepLL(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
       }
     }
   }
-  return finishFlagStep<SC>(c, r, s, a.rmask, a.smask);
+  return finishFlagStep<SC>(c, r, s, a.rmask, a.smask, (uint32_t)(npairs * 16), false);
 }
 
 // ------------------------------------------------------------------ LL128 datapath
@@ -782,6 +851,7 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
       }
     }
     if (!alive) break;
+    if constexpr (kJitter) jitterPause();  // a wave's line stores of this pass
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t line = lineOf[u];
@@ -813,7 +883,7 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
     }
   }
   if (!alive) atomicOr(c.sAbort, 1);
-  return finishFlagStep<SC>(c, r, s, a.rmask, a.smask);
+  return finishFlagStep<SC>(c, r, s, a.rmask, a.smask, nlines * LL128_LINE, true);
 }
 
 template <int PROTO, int SC, int DT, int OP>
@@ -1163,8 +1233,9 @@ __device__ void p2pTransfer(const Ctx& c, const WorkItem& w, const CollArgs& arg
 template <int PROTO, int SC, int DT, int OP>
 __device__ __noinline__ void runItem(const Ctx& c0, const WorkItem& w0, const CollArgs& args, uint64_t* sSteps) {
   Ctx c = uniformCtx(c0);
-  c.slotB = uniform((uint32_t)c.comm->slotBytes[PROTO]);
   const WorkItem w = uniformItem(w0);
+  // an item uses ring connections or tree connections, never both
+  c.slotB = uniform((uint32_t)(w.algo == ALGO_TREE ? c.comm->treeSlotBytes[PROTO] : c.comm->slotBytes[PROTO]));
   if constexpr (OP == OP_COPY) {
     if (w.coll == COLL_ALLGATHER) ringAllGather<PROTO, SC, DT, OP>(c, w, args, sSteps);
     else if (w.coll == COLL_BROADCAST) ringBroadcast<PROTO, SC, DT, OP>(c, w, args, sSteps);
@@ -1264,6 +1335,7 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
   __shared__ uint64_t sSteps[6];
   __shared__ int sAbort;
   __shared__ uint32_t sRole;
+  __shared__ uint64_t sWait;
 
   const uint32_t R = d.nranks;
   const DevComm* comm = d.comm;
@@ -1283,7 +1355,13 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
   c.nwaves = (blockDim.x + 63) >> 6;
   c.lid = threadIdx.x & 63;
   c.sAbort = &sAbort;
-  if (threadIdx.x == 0) sAbort = 0;
+  c.sWait = d.profile ? &sWait : nullptr;
+  if (threadIdx.x == 0) {
+    sAbort = 0;
+    sWait = 0;
+  }
+  const uint64_t tStart = d.profile ? nowTicks() : 0;
+  uint32_t nrun = 0;
 
   const bool inl = d.items == nullptr;
   const uint32_t first = inl ? lane : d.laneStart[lane];
@@ -1302,6 +1380,16 @@ __global__ void __launch_bounds__(1024) collKernel(const LaunchDesc d) {
     if (*(volatile int*)&sAbort) break;
     if (threadIdx.x == 0 && d.stamps && sItem.doneIndex != 0xFFFFFFFFu)
       d.stamps[(uint64_t)sItem.doneIndex * R + rank] = nowTicks();
+    ++nrun;
+  }
+  if (d.profile && threadIdx.x == 0) {
+    // this workgroup's span, the part of it spent waiting for counters, and
+    // its item count
+    uint64_t* rec = d.profile + ((uint64_t)lane * R + rank) * PROFILE_WORDS;
+    rec[0] = tStart;
+    rec[1] = nowTicks();
+    rec[2] = sWait;
+    rec[3] = nrun;
   }
 }
 
@@ -1346,6 +1434,7 @@ __global__ void __launch_bounds__(1024) serveKernel(const ServeDesc d) {
   c.nwaves = (blockDim.x + 63) >> 6;
   c.lid = threadIdx.x & 63;
   c.sAbort = &sAbort;
+  c.sWait = nullptr;
   if (threadIdx.x == 0) sAbort = 0;
   const bool leader = rank == 0;
   uint64_t* dbg = d.dbg + ((uint64_t)lane * R + rank) * SERVE_STRIDE_U64;

@@ -84,7 +84,7 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
     vcclResult_t r = planColl(c, colls[g], &plans[g], colls.size() == 1);
     if (r != vcclSuccess) return r;
     if (plans[g].algo == ALGO_TREE) {
-      r = cliqueEnsureTreeFifos(c);
+      r = cliqueEnsureTreeFifos(c, plans[g].proto);
       if (r != vcclSuccess) return r;
     }
   }
@@ -206,9 +206,15 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
   d.claimBase = c->claimBase;
   const int occ = cliqueOccupancy(c, block);
   if (grid > c->numCUs * occ) return vcclInternalError;
+  if (c->profile) {
+    d.profile = c->dProfile;
+    VCCL_HIPCHECK(hipMemsetAsync(c->dProfile, 0, (size_t)MAX_LANES * R * PROFILE_WORDS * sizeof(uint64_t),
+                                 ss.list[ss.n - 1]));
+  }
   r = launchPrepared(c, d, grid, block, ss);
   if (r != vcclSuccess) return r;
   c->lastStampColls = (int)colls.size();
+  c->lastLanes = nlanes;
   vcclPlanInfo_t& info = c->lastPlan;
   info.algo = plans[0].algo;
   info.proto = plans[0].proto;
@@ -609,6 +615,45 @@ vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int
   return vcclSuccess;
 }
 
+vcclResult_t vcclCommDebugProfile(vcclComm_t comm, int enable) {
+  if (!validHandle(comm)) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  VCCL_HIPCHECK(hipSetDevice(c->device));
+  VCCL_HIPCHECK(hipDeviceSynchronize());
+  if (enable && !c->dProfile)
+    VCCL_HIPCHECK(hipMalloc((void**)&c->dProfile, (size_t)MAX_LANES * c->nranks * PROFILE_WORDS * sizeof(uint64_t)));
+  c->profile = enable != 0;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommDebugReadProfile(vcclComm_t comm, uint64_t* out, int maxEntries, int* written) {
+  if (!validHandle(comm) || !out || !written) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  *written = 0;
+  if (!c->dProfile || c->lastLanes <= 0 || maxEntries <= 0) return vcclSuccess;
+  VCCL_HIPCHECK(hipEventSynchronize(c->lastLaunchDone));
+  const int n = std::min(maxEntries, c->lastLanes * c->nranks);
+  std::vector<uint64_t> raw((size_t)n * PROFILE_WORDS);
+  VCCL_HIPCHECK(hipMemcpy(raw.data(), c->dProfile, raw.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  const double nsPerTick = 1000.0 / c->ticksPerUs;
+  for (int k = 0; k < n; ++k) {
+    const uint64_t* rec = &raw[(size_t)k * PROFILE_WORDS];
+    out[4 * k + 0] = (uint64_t)((double)rec[0] * nsPerTick);
+    out[4 * k + 1] = (uint64_t)((double)rec[1] * nsPerTick);
+    out[4 * k + 2] = (uint64_t)((double)rec[2] * nsPerTick);
+    out[4 * k + 3] = rec[3];
+  }
+  *written = n;
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommGetTree(vcclComm_t comm, int tree, int* parents) {
+  if (!validHandle(comm) || !parents || tree < 0 || tree > 1) return vcclInvalidArgument;
+  const Clique* c = comm->clique;
+  for (int r = 0; r < c->nranks; ++r) parents[r] = c->host.parent[tree][r];
+  return vcclSuccess;
+}
+
 vcclResult_t vcclCommSetTimeout(vcclComm_t comm, uint64_t timeout_us) {
   if (!validHandle(comm) || timeout_us == 0) return vcclInvalidArgument;
   Clique* c = comm->clique;
@@ -660,6 +705,9 @@ vcclResult_t vcclDebugPlanHost(int nranks, int coll, size_t count, vcclDataType_
   c.host.slotBytes[PROTO_SIMPLE] = SLOT_BYTES_SIMPLE;
   c.host.slotBytes[PROTO_LL] = SLOT_BYTES_LL;
   c.host.slotBytes[PROTO_LL128] = SLOT_BYTES_LL128;
+  c.host.treeSlotBytes[PROTO_SIMPLE] = TREE_SLOT_BYTES_SIMPLE;
+  c.host.treeSlotBytes[PROTO_LL] = TREE_SLOT_BYTES_LL;
+  c.host.treeSlotBytes[PROTO_LL128] = TREE_SLOT_BYTES_LL128;
   c.deviceScopeBytes = 16 << 20;
   c.ll128 = ll128 != 0;
   buildTrees(nranks, 1, c.host.parent, c.host.child, c.host.childIdx, c.host.nchild);

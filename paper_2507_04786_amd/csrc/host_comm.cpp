@@ -159,6 +159,9 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   const uint64_t nconn = (uint64_t)c->maxLanes * nranks * NCONN;
   const uint64_t slot[3] = {(uint64_t)envLong("VCCL_SIMPLE_SLOT_BYTES", SLOT_BYTES_SIMPLE), SLOT_BYTES_LL,
                             SLOT_BYTES_LL128};
+  c->host.treeSlotBytes[PROTO_SIMPLE] = (uint64_t)envLong("VCCL_TREE_SIMPLE_SLOT_BYTES", TREE_SLOT_BYTES_SIMPLE);
+  c->host.treeSlotBytes[PROTO_LL] = TREE_SLOT_BYTES_LL;
+  c->host.treeSlotBytes[PROTO_LL128] = TREE_SLOT_BYTES_LL128;
   for (int p = 0; p < 3; ++p) {
     const uint64_t bytes = (uint64_t)c->maxLanes * nranks * NSLOTS * slot[p];  // ring connections
     e = hipMalloc((void**)&c->fifo[p], bytes);
@@ -276,6 +279,7 @@ void cliqueFree(Clique* c) {
   if (c->dLaneStart) hipFree(c->dLaneStart);
   if (c->dArgs) hipFree(c->dArgs);
   if (c->dStamps) hipFree(c->dStamps);
+  if (c->dProfile) hipFree(c->dProfile);
   for (int i = 0; i < 2; ++i) {
     if (c->hStage[i]) hipHostFree(c->hStage[i]);
     if (c->stageEvent[i]) hipEventDestroy(c->stageEvent[i]);
@@ -289,20 +293,28 @@ void cliqueFree(Clique* c) {
   delete c;
 }
 
-// Tree connections are allocated on the first tree launch (they are 6 of the
-// 7 connections of every lane and rank and only tree AllReduce uses them).
-vcclResult_t cliqueEnsureTreeFifos(Clique* c) {
-  if (c->treeFifo[0]) return vcclSuccess;
+// Tree connections of a protocol are allocated on the first tree launch
+// under that protocol (they are 6 of the 7 connections of every lane and
+// rank, and only tree AllReduce uses them).
+vcclResult_t cliqueEnsureTreeFifos(Clique* c, int proto) {
+  if (c->treeFifo[proto]) return vcclSuccess;
   VCCL_HIPCHECK(hipDeviceSynchronize());
-  for (int p = 0; p < 3; ++p) {
-    const uint64_t bytes = (uint64_t)c->maxLanes * c->nranks * NTREE_CONN * NSLOTS * c->host.slotBytes[p];
-    VCCL_HIPCHECK(hipMalloc((void**)&c->treeFifo[p], bytes));
-    if (p != PROTO_SIMPLE) VCCL_HIPCHECK(hipMemset(c->treeFifo[p], 0, bytes));
-    c->host.treeFifo[p] = c->treeFifo[p];
-  }
+  const uint64_t bytes = cliqueTreeFifoBytes(c, proto);
+  VCCL_HIPCHECK(hipMalloc((void**)&c->treeFifo[proto], bytes));
+  if (proto != PROTO_SIMPLE) VCCL_HIPCHECK(hipMemset(c->treeFifo[proto], 0, bytes));
+  c->host.treeFifo[proto] = c->treeFifo[proto];
   VCCL_HIPCHECK(hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice));
   VCCL_HIPCHECK(hipDeviceSynchronize());
+  logInfo("tree FIFOs, protocol %d: %.2f GiB", proto, (double)bytes / (1u << 30));
   return vcclSuccess;
+}
+
+uint64_t cliqueTreeFifoBytes(const Clique* c, int proto) {
+  return (uint64_t)c->maxLanes * c->nranks * NTREE_CONN * NSLOTS * c->host.treeSlotBytes[proto];
+}
+
+uint64_t cliqueRingFifoBytes(const Clique* c, int proto) {
+  return (uint64_t)c->maxLanes * c->nranks * NSLOTS * c->host.slotBytes[proto];
 }
 
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps) {

@@ -93,6 +93,9 @@ struct Clique {
   hipEvent_t stageEvent[2] = {nullptr, nullptr};
   int stageNext = 0;
   uint64_t* dStamps = nullptr;
+  uint64_t* dProfile = nullptr;   // per-workgroup records of profiling launches
+  bool profile = false;
+  int lastLanes = 0;              // lanes of the most recent launch
   size_t stampCap = 0;
   int lastStampColls = 0;
   hipEvent_t lastLaunchDone = nullptr;
@@ -126,7 +129,9 @@ int rankOf(vcclComm_t comm);
 // host_comm.cpp
 vcclResult_t cliqueCreate(int nranks, int device, Clique** out);
 void cliqueFree(Clique* c);
-vcclResult_t cliqueEnsureTreeFifos(Clique* c);
+vcclResult_t cliqueEnsureTreeFifos(Clique* c, int proto);
+uint64_t cliqueTreeFifoBytes(const Clique* c, int proto);
+uint64_t cliqueRingFifoBytes(const Clique* c, int proto);
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps);
 int cliqueOccupancy(Clique* c, int nthreads);
 void buildTrees(int nranks, int ranksPerNode, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2],

@@ -96,6 +96,7 @@ extern "C" vcclResult_t vcclAllReduceNoAlloc(const void* const* sendbuffs, void*
   dc.fifo[PROTO_LL] = nd.base + NA_OFF_FIFO_LL;
   dc.slotBytes[PROTO_SIMPLE] = NA_SLOT_SIMPLE;
   dc.slotBytes[PROTO_LL] = NA_SLOT_LL;
+  // ring only: no tree connections (treeFifo and treeSlotBytes stay zero)
   dc.ctr = (uint64_t*)(nd.base + NA_OFF_CTR);
   dc.abortFlag = (uint32_t*)(nd.base + NA_OFF_WORDS);
   dc.errorWord = (uint32_t*)(nd.base + NA_OFF_WORDS + 128);

@@ -34,11 +34,11 @@ static uint64_t unitsOf(uint8_t coll, size_t count, int dtype) {
   return copyOnly(coll) ? (uint64_t)count * dtypeBytes(dtype) : (uint64_t)count;
 }
 
-// Largest chunk one slot can carry per protocol (slot payload): the whole
-// slot under Simple, half of it under LL (4 data bytes per 8-byte unit),
-// 120 of every 128 bytes under LL128.
-static uint64_t maxChunkBytes(const Clique* c, int proto) {
-  const uint64_t slot = c->host.slotBytes[proto];
+// Largest chunk one slot of the algorithm's connections can carry per
+// protocol (slot payload): the whole slot under Simple, half of it under LL
+// (4 data bytes per 8-byte unit), 120 of every 128 bytes under LL128.
+static uint64_t maxChunkBytes(const Clique* c, int proto, int algo = ALGO_RING) {
+  const uint64_t slot = algo == ALGO_TREE ? c->host.treeSlotBytes[proto] : c->host.slotBytes[proto];
   if (proto == PROTO_SIMPLE) return slot;
   if (proto == PROTO_LL) return slot / 2;
   return slot / LL128_LINE * LL128_DATA;
@@ -177,7 +177,7 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
     nch = std::min(nch, std::max(1, (c->numCUs * occ) / R));
   }
   // --- chunk
-  const uint64_t maxChunk = maxChunkBytes(c, proto);
+  const uint64_t maxChunk = maxChunkBytes(c, proto, algo);
   uint64_t chunk;
   if (c->apiTune.chunkBytes) chunk = c->apiTune.chunkBytes;
   else if (c->envTune.chunkBytes) chunk = c->envTune.chunkBytes;
@@ -186,9 +186,9 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   else {
     if (proto == PROTO_SIMPLE && algo == ALGO_TREE) {
       // a tree pipelines chunks through 2 log2(R) hops: eight chunks per
-      // channel, at most 256 KiB (measured best for large trees)
+      // channel, at most a tree slot
       const uint64_t chBytes = ceilDiv(S, (uint64_t)nch);
-      chunk = std::min<uint64_t>(roundUp(std::max<uint64_t>(ceilDiv(chBytes, 8), 16 * 1024), 4096), 256 * 1024);
+      chunk = std::min<uint64_t>(roundUp(std::max<uint64_t>(ceilDiv(chBytes, 8), 16 * 1024), 4096), maxChunk);
     } else if (proto == PROTO_SIMPLE) {
       // a ring loop covers R chunks: take the largest chunk that still gives
       // every channel at least one full loop

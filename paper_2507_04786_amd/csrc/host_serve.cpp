@@ -132,7 +132,8 @@ uint64_t requestBytes(const Clique* c, const vcclRequest_t& r, const Plan& p) {
   uint64_t send = b, recv = b;
   if (r.coll == COLL_ALLGATHER) recv = b * R;
   if (r.coll == COLL_REDUCESCATTER) send = b * R;
-  const uint64_t fifo = (uint64_t)R * NSLOTS * c->host.slotBytes[p.proto];
+  const uint64_t fifo = p.algo == ALGO_TREE ? (uint64_t)R * NTREE_CONN * NSLOTS * c->host.treeSlotBytes[p.proto]
+                                            : (uint64_t)R * NSLOTS * c->host.slotBytes[p.proto];
   return (uint64_t)R * (send + recv) + (uint64_t)p.nchannels * fifo;
 }
 
@@ -239,8 +240,12 @@ vcclResult_t vcclServeCreate(vcclComm_t* comms, size_t budgetBytes, int lanes, v
   VCCL_HIPCHECK(hipSetDevice(c->device));
   // every allocation happens before the persistent kernel starts: a device
   // synchronisation while it runs would wait for its idle exit
-  vcclResult_t tr = cliqueEnsureTreeFifos(c);
-  if (tr != vcclSuccess) return tr;
+  // requests may plan trees under any protocol the set allows
+  for (int p = 0; p < 3; ++p) {
+    if (p == PROTO_LL128 && !c->ll128) continue;
+    vcclResult_t tr = cliqueEnsureTreeFifos(c, p);
+    if (tr != vcclSuccess) return tr;
+  }
   VCCL_HIPCHECK(hipDeviceSynchronize());
   vcclServer* s = new vcclServer();
   s->c = c;

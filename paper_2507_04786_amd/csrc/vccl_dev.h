@@ -5,7 +5,8 @@
 //       maxLanes * nranks connections of NSLOTS slots * slotBytes[p] each
 //       (index lane * nranks + receivingRank), and one for the tree
 //       connections (6 per lane and rank, index (lane * nranks + rank) * 6 +
-//       kind - 1), allocated on the first tree launch.
+//       kind - 1, slots of treeSlotBytes[p]), allocated on the first tree
+//       launch under protocol p.
 //     Connection id = (lane * nranks + receivingRank) * NCONN + kind, where kind
 //       0      ring: from the ring predecessor
 //       1, 2   tree 0: upward from the receiver's first / second child
@@ -35,13 +36,25 @@ constexpr int NCONN = 1 + NTREE_CONN;
 constexpr int MAX_RANKS = 16;
 constexpr int MAX_LANES = 64;
 constexpr int MAX_INLINE = 32;
-constexpr uint32_t SLOT_BYTES_SIMPLE = 512u * 1024u;
+// Slot sizes, ring and tree connections (Section V-C's channel-buffer table
+// gives NCCL's 512 KiB / 32 KiB / 600 KiB; a slot here holds the largest
+// chunk the planner can give its connections, no more): Simple 256 KiB for
+// the ring (the tuner's largest chunk), 128 KiB for the tree (its formula's
+// cap); LL 32 KiB (16 KiB of payload) for both; LL128 600 KiB (562.5 KiB of
+// payload) for the ring and 128 KiB (120 KiB) for the tree.
+constexpr uint32_t SLOT_BYTES_SIMPLE = 256u * 1024u;
 constexpr uint32_t SLOT_BYTES_LL = 32u * 1024u;
 constexpr uint32_t SLOT_BYTES_LL128 = 600u * 1024u;
+constexpr uint32_t TREE_SLOT_BYTES_SIMPLE = 128u * 1024u;
+constexpr uint32_t TREE_SLOT_BYTES_LL = 32u * 1024u;
+constexpr uint32_t TREE_SLOT_BYTES_LL128 = 128u * 1024u;
 constexpr uint32_t LL128_LINE = 128, LL128_DATA = 120;
 constexpr uint32_t CTR_RECORD_U64 = 32;  // 256 B per connection
 constexpr uint32_t CTR_HEAD_U64 = 16;    // head at +128 B
 constexpr uint32_t CLAIM_STRIDE_U64 = 16;
+// per-workgroup record of a profiling launch: first tick, last tick, ticks
+// spent waiting for counters, items run
+constexpr uint32_t PROFILE_WORDS = 4;
 
 // Store policy of a work item's traffic between the workgroups of a lane
 // (data, protocol lines and step counters; see device.hip): SCOPE_DEVICE --
@@ -61,7 +74,8 @@ struct DevComm {
   uint32_t scope;               // SCOPE_DEVICE or SCOPE_XCD for every launch of the set
   char* fifo[3];                // ring connections, per protocol
   char* treeFifo[3];            // tree connections, per protocol (null until first used)
-  uint64_t slotBytes[3];
+  uint64_t slotBytes[3];        // slot size of the ring connections, per protocol
+  uint64_t treeSlotBytes[3];    // slot size of the tree connections, per protocol
   uint64_t* ctr;                // counters
   uint32_t* abortFlag;          // host-pinned, written by the host
   uint32_t* errorWord;          // host-pinned, written by the device
@@ -105,6 +119,7 @@ struct LaunchDesc {
   const uint32_t* laneStart;    // nlanes + 1 offsets into items
   const CollArgs* args;         // pointer tables in device memory
   uint64_t* stamps;             // completion stamps [doneIndex * nranks + rank]
+  uint64_t* profile;            // profiling launches: PROFILE_WORDS per (lane, rank), else null
   uint32_t nlanes;
   uint32_t nranks;
   uint32_t xcdMap;              // 1: lane l's workgroups share XCD (l % 8)

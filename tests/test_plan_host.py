@@ -57,7 +57,9 @@ def test_plans_are_legal(vccl):
     payload, workgroup size 64..1024 in steps of 64, a grid that is resident
     at once (1024 / nthreads workgroups per compute unit, 256 units), trees
     only for AllReduce."""
-    payload = {0: 512 * 1024, 1: 16 * 1024, 2: 4800 * 120}
+    # slot payloads of the ring and the tree connections, per protocol
+    payload = {(0, 0): 256 * 1024, (0, 1): 16 * 1024, (0, 2): 4800 * 120,
+               (1, 0): 128 * 1024, (1, 1): 16 * 1024, (1, 2): 1024 * 120}
     for R in (2, 3, 4, 7, 8, 12, 16):
         lanes = max(32, min(64, (256 // R) // 8 * 8))
         for coll in COLLS:
@@ -65,7 +67,7 @@ def test_plans_are_legal(vccl):
                 for single in (0, 1):
                     p = vccl.vcclDebugPlanHost(R, coll, _count(coll, S, 4, R), vccl.vcclFloat32, single=single)
                     assert 1 <= p["nchannels"] <= lanes
-                    assert p["chunkBytes"] % 16 == 0 and 16 <= p["chunkBytes"] <= payload[p["proto"]]
+                    assert p["chunkBytes"] % 16 == 0 and 16 <= p["chunkBytes"] <= payload[(p["algo"], p["proto"])]
                     assert 64 <= p["nthreads"] <= 1024 and p["nthreads"] % 64 == 0
                     assert p["grid"] <= 256 * max(1, 1024 // p["nthreads"])
                     assert p["grid"] == 8 * R * ((p["nlanes"] + 7) // 8)

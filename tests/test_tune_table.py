@@ -52,10 +52,11 @@ def test_table_plans_are_legal():
         assert r["C"] in ts.CHANNELS, r
         # chunk and threads are those the measured plan ran with: a swept
         # value or the planner's formula (chunks of 4 KiB granules up to the
-        # Simple slot; workgroups of whole waves)
+        # Simple slot of the plan's connections, 256 KiB ring / 128 KiB
+        # tree; workgroups of whole waves)
         if r["chunk_kib"]:
             assert r["proto"] == 0 and r["lg"] >= ts.CHUNK_MIN_LOG2, r
-            assert r["chunk_kib"] % 4 == 0 and 16 <= r["chunk_kib"] <= 512, r
+            assert r["chunk_kib"] % 4 == 0 and 16 <= r["chunk_kib"] <= (128 if r["algo"] == 1 else 256), r
         if r["threads"]:
             assert r["lg"] >= (ts.CHUNK_MIN_LOG2 if r["proto"] == 0 else ts.THREADS_MIN_LOG2), r
             assert r["threads"] % 64 == 0 and 64 <= r["threads"] <= 1024, r
