@@ -743,6 +743,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=200, help="requests per rate before measurement")
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000,100000")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-workload", default="headline", choices=("headline", "ll", "ll128", "tree16"),
+                    help="with --profile-pass: the headline AllReduce, the same forced to LL or LL128, or the "
+                         "16-rank bf16 64 MiB tree AllReduce")
     ap.add_argument("--profile-pass", action="store_true",
                     help="for rocprofv3 counter runs: 3 plain 1 GiB device copies (calibration), "
                          "then `steps` AllReduces of the workload; prints nothing else")
@@ -809,13 +812,31 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
+        wl = args.profile_workload
+        if wl in ("ll", "ll128"):
+            vccl.vcclCommSetTuning(comms[0], algo=vccl.vcclAlgoRing, proto=vccl.PROTO_NAMES[wl])
+        if wl == "tree16":
+            for c in comms:
+                vccl.vcclCommDestroy(c)
+            R16, S16 = 16, 64 << 20
+            xb = si.rank_inputs(si.WL_TREE_AND_CHAINS, R16, "bfloat16", S16 // 2)
+            sends = [torch.from_numpy(x.view(np.int16)).cuda() for x in xb]
+            recvs = [torch.empty(S16 // 2, dtype=torch.int16, device="cuda") for _ in range(R16)]
+            comms = vccl.vcclCommInitAll(R16)
+            vccl.vcclCommSetTuning(comms[0], algo=vccl.vcclAlgoTree)
+
+            def step():
+                for r in range(R16):
+                    vccl.vcclAllReduce(sends[r], recvs[r], S16 // 2, vccl.vcclBfloat16, vccl.vcclSum, comms[r],
+                                       stream)
         for _ in range(args.steps):
             step()
         torch.cuda.synchronize()
         plan = vccl.vcclCommGetLastPlan(comms[0])
         for c in comms:
             vccl.vcclCommDestroy(c)
-        print(json.dumps({"profile_pass": True, "plan": plan, "copy_bytes": 2 * (1 << 30)}))
+        print(json.dumps({"profile_pass": True, "workload": wl, "plan": plan, "copy_bytes": 2 * (1 << 30)}))
         return
 
     # headline: tuner's plan

@@ -81,8 +81,8 @@ vcclResult_t vcclGetVersion(int* version); /* major*100 + minor */
  * must name the same device.  Allocates the FIFOs and counters of every
  * (channel, rank, connection) and builds the ring and the double binary tree
  * (Section II-C).  The set's lane limit (most channels a collective can use)
- * is the environment's VCCL_MAX_CHANNELS, else CUs / nranks rounded down to a
- * multiple of 8 and held to 32..64.  comms[] (caller-owned array of nranks
+ * is the environment's VCCL_MAX_CHANNELS, else 2 CUs / nranks rounded down to
+ * a multiple of 8 and held to 32..64 (64 up to 8 ranks on 256 CUs).  comms[] (caller-owned array of nranks
  * handles) receives one handle per rank.  Errors: vcclInvalidArgument for a bad count or device,
  * vcclUnhandledHipError if device memory cannot be obtained. */
 vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist);

@@ -817,16 +817,22 @@ __device__ bool stepLL128(const Ctx& c, Conn* r, Conn* s, const StepArgs& a) {
         for (int u = 0; u < U; ++u)
           v[u] = act[u] ? ldLine16<SC>(rin[i], lineOf[u] * LL128_LINE + 16u * j) : u32x4{0, 0, 0, 0};
         Spinner sp;
+        const uint64_t live = __ballot(1);
         for (;;) {
           // lane 7 of each line holds the flag; a line is re-read whole (one
-          // 8-lane load) until its flag is current
+          // 8-lane load) until its flag is current.  One ballot per group of
+          // lines tells every lane its line's state and the wave whether all
+          // lines are current.
           uint32_t pend = 0;
+          bool allOk = true;
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int flagOk = (!act[u] || j != 7 || ((((uint64_t)v[u].w << 32) | v[u].z) == flag)) ? 1 : 0;
-            if (__shfl(flagOk, c.lid | 7) == 0) pend |= 1u << u;
+            const bool flagOk = !act[u] || j != 7 || ((((uint64_t)v[u].w << 32) | v[u].z) == flag);
+            const uint64_t okMask = __ballot(flagOk);
+            allOk = allOk && okMask == live;
+            if (!((okMask >> (c.lid | 7)) & 1ull)) pend |= 1u << u;
           }
-          if (__all(pend == 0)) break;
+          if (allOk) break;
           if (__any(!sp.tick(c))) { alive = false; break; }
 #pragma unroll
           for (int u = 0; u < U; ++u)

@@ -96,7 +96,7 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
     double p2pBytes = 0;
     for (const auto& x : colls)
       if (x.coll == COLL_SENDRECV) p2pBytes += (double)x.count * dtypeBytes(x.dtype);
-    const int L = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
+    const int L = p2pLaneCap(c);
     for (size_t g = 0; g < colls.size() && p2pBytes > 0; ++g) {
       if (colls[g].coll != COLL_SENDRECV) continue;
       const double share = (double)colls[g].count * dtypeBytes(colls[g].dtype) / p2pBytes;
@@ -157,6 +157,10 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
     int maxCh = 1;
     for (const auto& p : plans) maxCh = std::max(maxCh, p.nchannels);
     nlanes = std::min<int>(capLanes, std::max<int>(maxCh, std::min<int>((int)items.size(), c->maxLanes)));
+    // a group of point-to-point copies only: one workgroup per CU
+    bool p2pOnly = true;
+    for (const auto& x : colls) p2pOnly = p2pOnly && x.coll == COLL_SENDRECV;
+    if (p2pOnly) nlanes = std::max(1, std::min(nlanes, p2pLaneCap(c)));
     std::vector<double> cost(items.size());
     for (size_t i = 0; i < items.size(); ++i) cost[i] = estimateCost(c, items[i]);
     std::vector<size_t> order(items.size());
@@ -699,7 +703,7 @@ vcclResult_t vcclDebugPlanHost(int nranks, int coll, size_t count, vcclDataType_
   Clique c;
   c.nranks = nranks;
   c.numCUs = 256;
-  c.maxLanes = std::max(32, std::min(MAX_LANES, (c.numCUs / nranks) / 8 * 8));
+  c.maxLanes = defaultLaneLimit(c.numCUs, nranks);
   for (int i = 1; i <= 16; ++i) c.occupancy[i] = std::max(1, 16 / i);
   c.host.scope = SCOPE_XCD;
   c.host.slotBytes[PROTO_SIMPLE] = SLOT_BYTES_SIMPLE;

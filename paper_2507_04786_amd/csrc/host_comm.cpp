@@ -128,6 +128,10 @@ void buildTrees(int R, int ranksPerNode, int8_t parent[2][MAX_RANKS], int8_t chi
   }
 }
 
+int defaultLaneLimit(int numCUs, int nranks) {
+  return std::max(32, std::min(MAX_LANES, (2 * numCUs / nranks) / 8 * 8));
+}
+
 vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   Clique* c = new Clique();
   c->nranks = nranks;
@@ -144,12 +148,13 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   if (e != hipSuccess) return fail(e, "hipSetDevice");
   e = hipDeviceGetAttribute(&c->numCUs, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return fail(e, "hipDeviceGetAttribute");
-  // lane limit: enough lanes to give every CU one workgroup (lanes come in
-  // eights, one per XCD), at least 32 and at most MAX_LANES.  FIFO memory
-  // scales with lanes x ranks, so a smaller set gets more lanes for the same
-  // memory: 4 ranks measured 20 % faster at 64 lanes than at 32.
-  const long dfltLanes = std::max(32, std::min(MAX_LANES, (c->numCUs / nranks) / 8 * 8));
-  c->maxLanes = (int)envLong("VCCL_MAX_CHANNELS", dfltLanes);
+  // lane limit: enough lanes to give every CU two workgroups (lanes come in
+  // eights, one per XCD), at least 32 and at most MAX_LANES: 64 up to 8
+  // ranks, 40 at 12, 32 at 16.  FIFO memory scales with lanes x ranks (at 8
+  // ranks and 64 lanes, 3.5 GiB of ring FIFOs).  4 ranks measured 20 %
+  // faster at 64 lanes than at 32; at 8 ranks, LL at 64 MiB 0.88 -> 0.82 ms
+  // with 64 lanes of 512 threads, and grouped batches run on more lanes.
+  c->maxLanes = (int)envLong("VCCL_MAX_CHANNELS", defaultLaneLimit(c->numCUs, nranks));
   if (c->maxLanes < 1) c->maxLanes = 1;
   if (c->maxLanes > MAX_LANES) c->maxLanes = MAX_LANES;
   int wallKHz = 0;

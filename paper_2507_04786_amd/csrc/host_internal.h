@@ -128,6 +128,7 @@ int rankOf(vcclComm_t comm);
 
 // host_comm.cpp
 vcclResult_t cliqueCreate(int nranks, int device, Clique** out);
+int defaultLaneLimit(int numCUs, int nranks);
 void cliqueFree(Clique* c);
 vcclResult_t cliqueEnsureTreeFifos(Clique* c, int proto);
 uint64_t cliqueTreeFifoBytes(const Clique* c, int proto);
@@ -147,6 +148,7 @@ void channelRange(uint64_t n, int nchannels, uint64_t align, int ch, uint64_t* s
 void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t argsIndex, uint32_t doneIndex,
                std::vector<WorkItem>* items);
 double estimateCost(const Clique* c, const WorkItem& w);
+int p2pLaneCap(const Clique* c);
 
 // host_api.cpp
 vcclResult_t launchColls(Clique* c, const std::vector<Coll>& colls);

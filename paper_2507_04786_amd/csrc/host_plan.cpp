@@ -87,6 +87,13 @@ void channelRange(uint64_t n, int nchannels, uint64_t align, int ch, uint64_t* s
   *count = e - s;
 }
 
+// Lanes point-to-point copies spread over: one workgroup per CU (at least
+// 32 lanes): copies have no waits to hide, and at 8 ranks 64 lanes (two
+// workgroups per CU) made the all-to-all 25 % slower than 32.
+int p2pLaneCap(const Clique* c) {
+  return std::max(1, std::min(c->maxLanes, std::max(32, c->numCUs / c->nranks)));
+}
+
 // Point-to-point transfer (Section II-A Send/Recv; Section II-C: grouped
 // transfers spread over channels; Section IV-A: P2P_DIRECT): a direct copy
 // into the receiver's buffer, a channel per 1 MiB up to the lane cap, every
@@ -96,7 +103,7 @@ static vcclResult_t planP2p(Clique* c, const Coll& coll, Plan* plan) {
   const int R = c->nranks;
   const uint64_t S = (uint64_t)coll.count * dtypeBytes(coll.dtype);
   auto pickPos = [&](long api, long env, long dflt) { return api > 0 ? api : (env > 0 ? env : dflt); };
-  const int laneCap = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
+  const int laneCap = p2pLaneCap(c);
   const long dfltC = (long)std::min<uint64_t>((uint64_t)laneCap, std::max<uint64_t>(1, ceilDiv(S, 1u << 20)));
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));
@@ -145,6 +152,12 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   // other moves data)
   const int laneCap = std::max(1, std::min(c->maxLanes, 2 * c->numCUs / R));
   long dfltC = te ? te->nchannels : (long)std::max<uint64_t>(1, std::min<uint64_t>(laneCap, S / (512 * 1024)));
+  // a flag protocol asked for where the table's plan is Simple, at 16 MiB and
+  // more: every lane (LL's lines in flight scale with the workgroups; at 8
+  // ranks and 64 MiB, 64 lanes of 512 threads beat 32 of 1024 by 7 %); the
+  // co-residency rule below trims it to what fits (LL128's 1024-thread
+  // workgroups: one per CU)
+  if (te && te->proto == PROTO_SIMPLE && proto != PROTO_SIMPLE && S >= (16u << 20)) dfltC = laneCap;
   dfltC = std::max(1L, std::min<long>(dfltC, laneCap));
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));

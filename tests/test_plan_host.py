@@ -61,7 +61,7 @@ def test_plans_are_legal(vccl):
     payload = {(0, 0): 256 * 1024, (0, 1): 16 * 1024, (0, 2): 4800 * 120,
                (1, 0): 128 * 1024, (1, 1): 16 * 1024, (1, 2): 1024 * 120}
     for R in (2, 3, 4, 7, 8, 12, 16):
-        lanes = max(32, min(64, (256 // R) // 8 * 8))
+        lanes = max(32, min(64, (2 * 256 // R) // 8 * 8))
         for coll in COLLS:
             for S in SIZES:
                 for single in (0, 1):
