@@ -26,8 +26,9 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
               log-uniform) replayed through the continuous-batching server at
               several arrival rates: p50 / p99 latency, offered vs achieved rate
   cpu_baseline the CPU oracle (numpy schedule simulation) on the same inputs
-              and plan, and a spot check of the timed launch's result
-              against the oracle's fold (4096 samples, bit for bit)
+              and plan, timed on the host's cores, and the timed launch's
+              result checked bit for bit on every element against the
+              oracle's step simulation and its closed-form fold
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib 64]
                        [--no-cpu] [--no-protocols] [--no-grouped] [--no-serving]
@@ -451,7 +452,10 @@ def grouped_leg(vccl, torch, si, comms, stream, seeds=10, reps=3):
 
             def batch(group, device_only):
                 if device_only and spin is not None:
-                    spin(2_000_000)  # the device waits here while the host issues the batch
+                    # about 3.3 ms: longer than the host takes to issue a per-call
+                    # batch (512 calls and 64 launches, about 1.3 ms), so the
+                    # launches queue up and run back to back
+                    spin(8_000_000)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 evs = []
