@@ -24,7 +24,12 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
               collectives; bit equality of the two paths is checked
   serving     Poisson request streams (AR 60 % / AG 20 % / RS 20 %, 1 KiB..128 MiB
               log-uniform) replayed through the continuous-batching server at
-              several arrival rates: p50 / p99 latency, offered vs achieved rate
+              several arrival rates, and the same streams through one launch
+              per request: p50 / p99 latency overall and per size bucket,
+              offered vs achieved rate; a server of 32 lanes ('serving', one
+              workgroup per CU) and of 64 ('serving_lanes64': a request of
+              16 MiB or more holds half the lanes, so small requests run
+              beside it)
   cpu_baseline the CPU oracle (numpy schedule simulation) on the same inputs
               and plan, timed on the host's cores, and the timed launch's
               result checked bit for bit on every element against the
@@ -32,7 +37,7 @@ eight per-rank calls, matched into one launch).  Prints ONE JSON line:
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size-mib 64]
                        [--no-cpu] [--no-protocols] [--no-grouped] [--no-serving]
-                       [--no-collectives]
+                       [--no-collectives] [--serve-lanes 32,64]
 """
 from __future__ import annotations
 
@@ -746,6 +751,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=200, help="requests per rate before measurement")
     ap.add_argument("--serve-rates", default="1000,2000,5000,10000,20000,50000,100000")
+    ap.add_argument("--serve-lanes", default="32,64",
+                    help="lanes of the server; the first gives 'serving', each further one 'serving_lanes<L>'")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-workload", default="headline", choices=("headline", "ll", "ll128", "tree16"),
                     help="with --profile-pass: the headline AllReduce, the same forced to LL or LL128, or the "
@@ -905,10 +912,16 @@ def main():
     if not args.no_collectives:
         colls16 = collectives_leg(vccl, torch, si)
         a2a = alltoall_leg(vccl, torch, si)
-    serving = None
+    serving, serving_more = None, {}
     if not args.no_serving:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
-        serving = serving_leg(vccl, torch, si, R, rates, args.serve_requests, args.serve_warmup)
+        lane_counts = [int(x) for x in args.serve_lanes.split(",") if x]
+        for i, L in enumerate(lane_counts):
+            res = serving_leg(vccl, torch, si, R, rates, args.serve_requests, args.serve_warmup, lanes=L)
+            if i == 0:
+                serving = res
+            else:
+                serving_more[f"serving_lanes{L}"] = res
 
     out = {
         "metric": METRIC,
@@ -942,6 +955,7 @@ def main():
         "alltoall": a2a,
         "grouped": grouped,
         "serving": serving,
+        **serving_more,
         "cpu_baseline": cpu,
     }
     if pool is not None:

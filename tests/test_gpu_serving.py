@@ -77,12 +77,15 @@ def _snapshot(bufs, reqs):
     return [[H.from_dev(r, req[1]).copy() for r in buf[1]] for buf, req in zip(bufs, reqs)]
 
 
-def test_alone_equals_mix_and_oracle(vccl):
+@pytest.mark.parametrize("lanes", [16, 64])
+def test_alone_equals_mix_and_oracle(vccl, lanes):
+    """lanes 64: the set's lane limit at 8 ranks, two workgroups per CU."""
+    print(f"serving alone/mix lanes={lanes}", flush=True)
     comms = vccl.vcclCommInitAll(R)
     try:
         reqs = _requests(1, 40, 1024, 4 << 20)
         bufs = _buffers(reqs)
-        srv = vccl.vcclServeCreate(comms, 4 << 30, 16)
+        srv = vccl.vcclServeCreate(comms, 4 << 30, lanes)
         try:
             alone = []
             plans = {}
