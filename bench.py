@@ -67,6 +67,12 @@ def alg_bytes_per_launch(plan: dict, nranks: int, size: int) -> float:
     return (2 * R + 4 * f * (R - 1)) * size
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as each leg of the run ends (the JSON line stays
+    alone on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_digest() -> str:
     """Digest of what decides the launch's memory traffic: the kernel's
     sources (device code and the structures it shares with the host), the
@@ -873,6 +879,7 @@ def main():
     achieved = abytes / ev_step / 1e9
     key = f"collKernel_ring_allreduce_r{R}_{args.size_mib}MiB_fp32"
     traffic = load_traffic(key)
+    progress(f"headline done: {ev_step * 1e3:.4f} ms per launch")
 
     protos = {}
     sizes = None
@@ -888,8 +895,10 @@ def main():
                             "ms": round(e * 1e3, 4), "nchannels": p["nchannels"], "chunk_bytes": p["chunkBytes"],
                             "direct": p["direct"]}
         vccl.vcclCommSetTuning(comms[0])
+        progress("protocols done")
         sizes = sizes_leg(vccl, torch, comms, sends, recvs, stream)
         large = large_leg(vccl, torch, comms, sends, stream)
+        progress("sizes done")
 
     cpu = None
     if not args.no_cpu:
@@ -900,10 +909,12 @@ def main():
         gpu_out = recvs[0].cpu().numpy()
         cpu = cpu_baseline_leg(pool, nworkers, xs, plan, R, S, args.cpu_seconds, gpu_out)
         del gpu_out
+        progress("cpu baseline done")
 
     grouped = None
     if not args.no_grouped:
         grouped = grouped_leg(vccl, torch, si, comms, stream)
+        progress("grouped done")
     for c in comms:
         vccl.vcclCommDestroy(c)
     del sends, recvs
@@ -912,12 +923,14 @@ def main():
     if not args.no_collectives:
         colls16 = collectives_leg(vccl, torch, si)
         a2a = alltoall_leg(vccl, torch, si)
+        progress("16-rank collectives and all-to-all done")
     serving, serving_more = None, {}
     if not args.no_serving:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         lane_counts = [int(x) for x in args.serve_lanes.split(",") if x]
         for i, L in enumerate(lane_counts):
             res = serving_leg(vccl, torch, si, R, rates, args.serve_requests, args.serve_warmup, lanes=L)
+            progress(f"serving with {L} lanes done")
             if i == 0:
                 serving = res
             else:
