@@ -960,7 +960,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic / ev_step / 1e9, 1),
                      "kernel": "vccl::collKernel", "alg_bytes_per_launch": abytes,
-                     "avg_launch_ms": round(ev_step * 1e3, 4)},
+                     "avg_launch_ms": round(ev_step * 1e3, 4),
+                     # the bytes no schedule can avoid (every input read and
+                     # every output written once, 2 R S) per launch time
+                     "compulsory_frac": round(2 * R * S / ev_step / 1e9 / HBM_PEAK_GBS, 4)},
         "protocols": protos,
         "sizes": sizes,
         "large_sizes": large,
