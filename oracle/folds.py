@@ -13,6 +13,11 @@ simulator changes the order and the bits):
 * Ring Reduce: folded over ``root+1, root+2, ..., root``.
 * Tree AllReduce: post-order on the channel's tree:
   ``f(v) = op(op(x_v, f(first child)), f(second child))``.
+* With per-channel ring orders (``rings``; Section II-C) the ring folds run
+  over ring positions: segment ``s`` of a channel is folded over the ranks
+  at positions ``s+1, ..., s+R`` of that channel's ring, block ``b`` over
+  the ranks that follow rank ``b`` on the ring, and a Reduce over the ranks
+  that follow the root, ending at the root.
 
 The segment of an element is computed arithmetically from the partition
 reading (``partition`` module) rather than by walking loop lists.
@@ -52,7 +57,20 @@ def ring_allreduce_segment_of(idx, n, nranks, nchannels, chunk, align):
     return np.where(in_full, seg_full, seg_last)
 
 
-def ring_allreduce(xs, op, dtype, nchannels, chunk, idx=None):
+def _channel_of(idx, n, nchannels, align):
+    per = pt.round_up(pt.ceil_div(n, nchannels), align) if n > 0 else 1
+    return np.asarray(idx, dtype=np.int64) // per
+
+
+def _ring_orders(R, idx, n, nchannels, align, rings):
+    """(channel ring order, mask of idx on channels with that order) pairs."""
+    if rings is None:
+        return [(list(range(R)), np.ones(len(idx), dtype=bool))]
+    chan = _channel_of(idx, n, nchannels, align)
+    return [(topo.channel_ring(R, k, rings), (chan % len(rings)) == k) for k in range(len(rings))]
+
+
+def ring_allreduce(xs, op, dtype, nchannels, chunk, idx=None, rings=None):
     """Expected AllReduce output (identical on all ranks) at ``idx`` (default all)."""
     R = len(xs)
     n = len(xs[0])
@@ -62,34 +80,52 @@ def ring_allreduce(xs, op, dtype, nchannels, chunk, idx=None):
     idx = np.asarray(idx, dtype=np.int64)
     seg = ring_allreduce_segment_of(idx, n, R, nchannels, chunk, A)
     out = np.empty(len(idx), dtype=np.asarray(xs[0]).dtype)
-    for s in range(R):
-        m = seg == s
-        if not m.any():
-            continue
-        order = [(s + 1 + j) % R for j in range(R)]
-        out[m] = _fold([np.asarray(xs[q])[idx[m]] for q in order], op, dtype)
+    for ring, on in _ring_orders(R, idx, n, nchannels, A, rings):
+        for s in range(R):
+            m = on & (seg == s)
+            if not m.any():
+                continue
+            order = [ring[(s + 1 + j) % R] for j in range(R)]
+            out[m] = _fold([np.asarray(xs[q])[idx[m]] for q in order], op, dtype)
     return out
 
 
-def ring_reducescatter(xs, op, dtype, rank, idx=None):
-    """Expected ReduceScatter output of ``rank`` at ``idx`` (default all)."""
+def ring_reducescatter(xs, op, dtype, rank, idx=None, nchannels=1, rings=None):
+    """Expected ReduceScatter output of ``rank`` at ``idx`` (default all).
+    ``nchannels`` matters only with ``rings``."""
     R = len(xs)
     n = len(xs[0]) // R
+    A = pt.align_units("reducescatter", ew.ELEM_BYTES[dtype])
     if idx is None:
         idx = np.arange(n)
     idx = np.asarray(idx, dtype=np.int64)
-    order = [(rank + 1 + j) % R for j in range(R)]
-    return _fold([np.asarray(xs[q])[rank * n + idx] for q in order], op, dtype)
+    out = np.empty(len(idx), dtype=np.asarray(xs[0]).dtype)
+    for ring, m in _ring_orders(R, idx, n, nchannels, A, rings):
+        if not m.any():
+            continue
+        q0 = ring.index(rank)
+        order = [ring[(q0 + 1 + j) % R] for j in range(R)]
+        out[m] = _fold([np.asarray(xs[q])[rank * n + idx[m]] for q in order], op, dtype)
+    return out
 
 
-def ring_reduce(xs, op, dtype, root, idx=None):
+def ring_reduce(xs, op, dtype, root, idx=None, nchannels=1, rings=None):
+    """Expected Reduce output at the root, at ``idx`` (default all).
+    ``nchannels`` matters only with ``rings``."""
     R = len(xs)
     n = len(xs[0])
+    A = pt.align_units("reduce", ew.ELEM_BYTES[dtype])
     if idx is None:
         idx = np.arange(n)
     idx = np.asarray(idx, dtype=np.int64)
-    order = [(root + 1 + j) % R for j in range(R)]
-    return _fold([np.asarray(xs[q])[idx] for q in order], op, dtype)
+    out = np.empty(len(idx), dtype=np.asarray(xs[0]).dtype)
+    for ring, m in _ring_orders(R, idx, n, nchannels, A, rings):
+        if not m.any():
+            continue
+        q0 = ring.index(root)
+        order = [ring[(q0 + 1 + j) % R] for j in range(R)]
+        out[m] = _fold([np.asarray(xs[q])[idx[m]] for q in order], op, dtype)
+    return out
 
 
 def tree_allreduce(xs, op, dtype, nchannels, idx=None, ranks_per_node=1):

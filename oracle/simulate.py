@@ -24,6 +24,13 @@ Readings adopted where the paper is silent (the library follows the same):
   (AllGather); so rank ``p`` ends the reduction phase owning segment ``p``.
 * Broadcast chain: root, root+1, ..., root-1.  Reduce chain: root+1, ...,
   root-1, root (the "first GPU" is the root's successor).
+* A channel may follow another ring order (``rings``, Section II-C; see
+  ``topology.channel_ring``).  Every rule above then reads positions on the
+  channel's ring for rank numbers: the rank at position ``q`` sends to the
+  one at ``q + 1`` and works on segment ``(q - 1 - t) mod R``, the
+  ReduceScatter and AllGather blocks are those of the ranks at positions
+  ``(q - 1 - t)`` and ``(q - t)``, and the chains run along the ring from
+  the root (Broadcast) or from the root's successor to the root (Reduce).
 * A reduction step computes ``op(received, local)``; a tree node with two
   children computes ``op(op(local, first child), second child)``.
 * Channel ``c`` of a tree AllReduce uses tree ``c mod 2`` of the double
@@ -145,7 +152,7 @@ def _ring_ar_prim(t: int, nranks: int) -> str:
     return "recv"
 
 
-def ring_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=None):
+def ring_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=None, rings=None):
     """Ring AllReduce of equal-length per-rank arrays; returns per-rank outputs."""
     R = len(xs)
     n = len(xs[0])
@@ -154,13 +161,15 @@ def ring_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=N
     outs = [np.zeros_like(x) for x in xs]
     for c, (cs, ce) in enumerate(pt.channel_ranges(n, nchannels, A)):
         loops = pt.ring_allreduce_loops(ce - cs, R, chunk, A) if ce > cs else []
+        order = topo.channel_ring(R, c, rings)
         programs = {}
         for p in range(R):
             prog = []
-            nxt, prv = topo.ring_next(p, R), topo.ring_prev(p, R)
+            q = order.index(p)
+            nxt, prv = order[(q + 1) % R], order[(q - 1) % R]
             for l, segs in enumerate(loops):
                 for t in range(2 * R - 1):
-                    s = (p - 1 - t) % R
+                    s = (q - 1 - t) % R
                     a, b = cs + segs[s][0], cs + segs[s][1]
                     prim = _ring_ar_prim(t, R)
                     recv = [("ring", prv, p)] if prim != "send" else []
@@ -175,7 +184,7 @@ def ring_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=N
     return outs
 
 
-def ring_reducescatter(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=None):
+def ring_reducescatter(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=None, rings=None):
     """xs[p] holds R blocks of n elements; rank p receives the reduced block p."""
     R = len(xs)
     n = len(xs[0]) // R
@@ -184,14 +193,16 @@ def ring_reducescatter(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, tra
     outs = [np.zeros(n, dtype=xs[0].dtype) for _ in xs]
     for c, (cs, ce) in enumerate(pt.channel_ranges(n, nchannels, A)):
         chunks = pt.chunk_ranges(ce - cs, chunk) if ce > cs else []
+        order = topo.channel_ring(R, c, rings)
         programs = {}
         for p in range(R):
             prog = []
-            nxt, prv = topo.ring_next(p, R), topo.ring_prev(p, R)
+            q = order.index(p)
+            nxt, prv = order[(q + 1) % R], order[(q - 1) % R]
             for l, (a0, b0) in enumerate(chunks):
                 a, b = cs + a0, cs + b0
                 for t in range(R):
-                    j = (p - 1 - t) % R
+                    j = order[(q - 1 - t) % R]
                     if t == 0:
                         prim = "send"
                     elif t <= R - 2:
@@ -212,7 +223,7 @@ def _as_bytes(x):
     return np.ascontiguousarray(x).view(np.uint8)
 
 
-def ring_allgather(xs, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS, trace=None):
+def ring_allgather(xs, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS, trace=None, rings=None):
     """xs[p] holds n elements; every rank receives the R blocks in rank order."""
     R = len(xs)
     xb = [_as_bytes(x) for x in xs]
@@ -221,14 +232,16 @@ def ring_allgather(xs, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS, trace
     A = pt.align_units("allgather", ew.ELEM_BYTES[dtype])
     for c, (cs, ce) in enumerate(pt.channel_ranges(nb, nchannels, A)):
         chunks = pt.chunk_ranges(ce - cs, chunk_bytes) if ce > cs else []
+        order = topo.channel_ring(R, c, rings)
         programs = {}
         for p in range(R):
             prog = []
-            nxt, prv = topo.ring_next(p, R), topo.ring_prev(p, R)
+            q = order.index(p)
+            nxt, prv = order[(q + 1) % R], order[(q - 1) % R]
             for l, (a0, b0) in enumerate(chunks):
                 a, b = cs + a0, cs + b0
                 for t in range(R):
-                    j = (p - t) % R
+                    j = order[(q - t) % R]
                     if t == 0:
                         prim, recv, send, src = "copySend", [], [("ring", p, nxt)], (xb[p], a, b)
                     elif t <= R - 2:
@@ -242,8 +255,8 @@ def ring_allgather(xs, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS, trace
     return [o.view(xs[0].dtype) for o in outs_b]
 
 
-def ring_broadcast(xs, root, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS, trace=None):
-    """Chain root -> root+1 -> ... -> root-1; every rank receives xs[root]."""
+def ring_broadcast(xs, root, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS, trace=None, rings=None):
+    """Chain from the root along the ring; every rank receives xs[root]."""
     R = len(xs)
     xb = [_as_bytes(x) for x in xs]
     nb = len(xb[0])
@@ -251,10 +264,12 @@ def ring_broadcast(xs, root, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS,
     A = pt.align_units("broadcast", ew.ELEM_BYTES[dtype])
     for c, (cs, ce) in enumerate(pt.channel_ranges(nb, nchannels, A)):
         chunks = pt.chunk_ranges(ce - cs, chunk_bytes) if ce > cs else []
+        order = topo.channel_ring(R, c, rings)
         programs = {}
         for p in range(R):
-            pos = (p - root) % R
-            nxt, prv = topo.ring_next(p, R), topo.ring_prev(p, R)
+            q = order.index(p)
+            pos = (q - order.index(root)) % R
+            nxt, prv = order[(q + 1) % R], order[(q - 1) % R]
             prog = []
             for l, (a0, b0) in enumerate(chunks):
                 a, b = cs + a0, cs + b0
@@ -272,18 +287,21 @@ def ring_broadcast(xs, root, dtype, nchannels, chunk_bytes, slots=DEFAULT_SLOTS,
     return [o.view(xs[0].dtype) for o in outs_b]
 
 
-def ring_reduce(xs, root, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=None):
-    """Chain root+1 -> ... -> root; returns the root's output (others None)."""
+def ring_reduce(xs, root, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, trace=None, rings=None):
+    """Chain along the ring from the root's successor to the root; returns
+    the root's output (others None)."""
     R = len(xs)
     n = len(xs[0])
     A = pt.align_units("reduce", ew.ELEM_BYTES[dtype])
     out = np.zeros_like(xs[root])
     for c, (cs, ce) in enumerate(pt.channel_ranges(n, nchannels, A)):
         chunks = pt.chunk_ranges(ce - cs, chunk) if ce > cs else []
+        order = topo.channel_ring(R, c, rings)
         programs = {}
         for p in range(R):
-            pos = (p - root - 1) % R
-            nxt, prv = topo.ring_next(p, R), topo.ring_prev(p, R)
+            q = order.index(p)
+            pos = (q - order.index(root) - 1) % R
+            nxt, prv = order[(q + 1) % R], order[(q - 1) % R]
             prog = []
             for l, (a0, b0) in enumerate(chunks):
                 a, b = cs + a0, cs + b0
@@ -349,7 +367,7 @@ def tree_allreduce(xs, op, dtype, nchannels, chunk, slots=DEFAULT_SLOTS, lag=0, 
 
 
 def run(coll, xs, *, op="sum", dtype, nchannels=1, chunk_bytes, root=0, algo="ring",
-        slots=DEFAULT_SLOTS, lag=0, trace=None, ranks_per_node=1):
+        slots=DEFAULT_SLOTS, lag=0, trace=None, ranks_per_node=1, rings=None):
     """Dispatch by collective name; chunk_bytes is converted to partition units."""
     E = ew.ELEM_BYTES[dtype]
     ub = pt.unit_bytes(coll, E)
@@ -359,13 +377,13 @@ def run(coll, xs, *, op="sum", dtype, nchannels=1, chunk_bytes, root=0, algo="ri
     if coll == "allreduce":
         if algo == "tree":
             return tree_allreduce(xs, op, dtype, nchannels, K, slots, lag, trace, ranks_per_node)
-        return ring_allreduce(xs, op, dtype, nchannels, K, slots, trace)
+        return ring_allreduce(xs, op, dtype, nchannels, K, slots, trace, rings)
     if coll == "reducescatter":
-        return ring_reducescatter(xs, op, dtype, nchannels, K, slots, trace)
+        return ring_reducescatter(xs, op, dtype, nchannels, K, slots, trace, rings)
     if coll == "allgather":
-        return ring_allgather(xs, dtype, nchannels, K, slots, trace)
+        return ring_allgather(xs, dtype, nchannels, K, slots, trace, rings)
     if coll == "broadcast":
-        return ring_broadcast(xs, root, dtype, nchannels, K, slots, trace)
+        return ring_broadcast(xs, root, dtype, nchannels, K, slots, trace, rings)
     if coll == "reduce":
-        return ring_reduce(xs, root, op, dtype, nchannels, K, slots, trace)
+        return ring_reduce(xs, root, op, dtype, nchannels, K, slots, trace, rings)
     raise ValueError(coll)

@@ -2,7 +2,9 @@
 Channels; Section V-E for the direction of the ring).
 
 Ring: rank ``p`` sends to ``(p + 1) % R`` and receives from ``(p - 1) % R``
-(the ReduceScatter description names ``(i+1)%k`` as the destination).
+(the ReduceScatter description names ``(i+1)%k`` as the destination).  A
+set may give its channels other ring orders (``channel_ring``); the step
+tables then apply to ring positions instead of rank numbers.
 
 Double binary tree: the paper states only its properties -- no rank is an
 inner node of both trees, at most one rank is a leaf in both, and the second
@@ -29,6 +31,21 @@ def ring_next(p: int, nranks: int) -> int:
 
 def ring_prev(p: int, nranks: int) -> int:
     return (p - 1) % nranks
+
+
+def channel_ring(nranks: int, channel: int, rings=None) -> list[int]:
+    """The ring order of a channel (Section II-C: each channel has its own
+    logical ring, set up at initialisation).  ``rings`` is None (every
+    channel on the identity ring, rank p sending to p + 1) or a list of ring
+    orders, each listing the ranks in ring order; channel c follows
+    ``rings[c % len(rings)]`` (a reading: the paper does not say how channels
+    map to rings).  Returns the order after checking it is a permutation."""
+    if rings is None:
+        return list(range(nranks))
+    order = [int(r) for r in rings[channel % len(rings)]]
+    if sorted(order) != list(range(nranks)):
+        raise ValueError("a ring order must be a permutation of the ranks")
+    return order
 
 
 def _lowbit(q: int) -> int:

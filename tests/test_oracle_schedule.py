@@ -399,10 +399,10 @@ def test_pins_catch_wrong_segment_index(monkeypatch):
     """A plausible slip (segment p - t instead of p - 1 - t) must fail a pin."""
     orig = sim.ring_allreduce
 
-    def wrong(xs, op, dtype, nchannels, chunk, slots=8, trace=None):
+    def wrong(xs, op, dtype, nchannels, chunk, slots=8, trace=None, rings=None):
         R = len(xs)
         rot = [np.asarray(xs[(p + 1) % R]) for p in range(R)]
-        return orig(rot, op, dtype, nchannels, chunk, slots, trace)
+        return orig(rot, op, dtype, nchannels, chunk, slots, trace, rings)
 
     monkeypatch.setattr(sim, "ring_allreduce", wrong)
     xs = si.rank_inputs(4, 5, "float32", 500)
