@@ -48,6 +48,7 @@ extern "C" {
 #define VCCL_MINOR 1
 #define VCCL_MAX_RANKS 16
 #define VCCL_MAX_CHANNELS 64
+#define VCCL_MAX_RINGS 4
 
 typedef struct vcclComm* vcclComm_t;
 
@@ -79,13 +80,36 @@ vcclResult_t vcclGetVersion(int* version); /* major*100 + minor */
  * (2..16) virtual-rank communicators on one device: devlist == NULL uses the
  * current HIP device, otherwise devlist[0] names it and every other entry
  * must name the same device.  Allocates the FIFOs and counters of every
- * (channel, rank, connection) and builds the ring and the double binary tree
- * (Section II-C).  The set's lane limit (most channels a collective can use)
+ * (channel, rank, connection) and builds the ring (rank p sends to p + 1 on
+ * every channel) and the double binary tree (Section II-C).  The set's lane limit (most channels a collective can use)
  * is the environment's VCCL_MAX_CHANNELS, else 2 CUs / nranks rounded down to
  * a multiple of 8 and held to 32..64 (64 up to 8 ranks on 256 CUs).  comms[] (caller-owned array of nranks
  * handles) receives one handle per rank.  Errors: vcclInvalidArgument for a bad count or device,
  * vcclUnhandledHipError if device memory cannot be obtained. */
 vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist);
+
+/* vcclCommInitAll with the ring of every channel given (Section II-C: each
+ * channel has its own ring, in which every rank knows its predecessor and
+ * successor, set up at initialisation and kept for every collective).
+ * rings: a caller-owned host array of nrings rows of nranks entries; row k
+ * lists the ranks in ring order (rank rings[k*nranks + q] sends to the rank
+ * at q + 1, the last to the first) and must be a permutation of
+ * 0..nranks-1.  Channel c of a ring collective follows row c mod nrings,
+ * wherever it runs (launched alone, in a group or served), so a collective's
+ * bits depend on its channel count, not on how it was launched.  Tree
+ * AllReduce and Send/Recv do not use the rings.  Ring-order k > 0 has FIFOs
+ * of its own: the set's ring FIFO memory grows nrings-fold.  rings == NULL
+ * (nrings ignored) is vcclCommInitAll.  vcclInvalidArgument for nrings
+ * outside 1..VCCL_MAX_RINGS or a row that is not a permutation, otherwise as
+ * vcclCommInitAll. */
+vcclResult_t vcclCommInitAllRings(vcclComm_t* comms, int nranks, const int* devlist, int nrings, const int* rings);
+
+/* The set's ring orders: *nrings receives their count, and, when rings is
+ * not NULL, rings[k*nranks + q] the rank at position q of ring k (a
+ * caller-owned host array of at least *nrings x nranks entries; ask with
+ * rings == NULL first for the count).  vcclInvalidArgument for an unknown
+ * handle or a null nrings. */
+vcclResult_t vcclCommGetRings(vcclComm_t comm, int* nrings, int* rings);
 
 /* Section II-A: ncclCommDestroy completes pending operations, then frees.
  * Destroying any rank's handle waits for all work of the set and frees the
@@ -250,7 +274,7 @@ vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int
  * ranks of send[q][i].  `stream` is a hipStream_t as void*; plan (may be
  * NULL, caller-owned host memory) receives the plan that ran.
  * Everything beyond the caller's buffers lives in one file-scope device
- * array of 40.25 MiB per device (the descriptor, the counters of at most 128
+ * array of 40.5 MiB per device (the descriptor, the counters of at most 128
  * lanes x ranks, 8 Simple slots of 32 KiB and 8 LL slots of 8 KiB per
  * connection): channels are limited to min(32, 128 / nranks), Simple chunks
  * to 32 KiB, LL chunks to 4 KiB; the protocol is Simple or LL, never LL128,

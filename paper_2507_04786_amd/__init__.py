@@ -89,6 +89,8 @@ def _load():
         "vcclGetErrorString": (C.c_char_p, [I]),
         "vcclGetVersion": (I, [C.POINTER(I)]),
         "vcclCommInitAll": (I, [C.POINTER(P), I, C.POINTER(I)]),
+        "vcclCommInitAllRings": (I, [C.POINTER(P), I, C.POINTER(I), I, C.POINTER(I)]),
+        "vcclCommGetRings": (I, [P, C.POINTER(I), C.POINTER(I)]),
         "vcclCommDestroy": (I, [P]),
         "vcclCommAbort": (I, [P]),
         "vcclCommGetAsyncError": (I, [P, C.POINTER(I)]),
@@ -159,7 +161,7 @@ EXPORTED = ("vcclGetErrorString vcclGetVersion vcclCommInitAll vcclCommDestroy v
             "vcclProbeLL128Tear vcclProbeXccIds vcclServeCreate vcclServeSubmit vcclServeTest "
             "vcclServeDestroy vcclServeReplay vcclServeDebugState vcclServeGetPlan vcclDebugPlanHost "
             "vcclReplayPerCall vcclAllReduceNoAlloc vcclCommDebugProfile vcclCommDebugReadProfile "
-            "vcclCommGetTree").split()
+            "vcclCommGetTree vcclCommInitAllRings vcclCommGetRings").split()
 
 
 def lib():
@@ -197,12 +199,32 @@ def vcclGetVersion() -> int:
     return v.value
 
 
-def vcclCommInitAll(nranks: int, devlist=None) -> list:
+def vcclCommInitAll(nranks: int, devlist=None, rings=None) -> list:
+    """rings: None (every channel on the identity ring) or a list of ring
+    orders, each a permutation of range(nranks); channel c follows
+    rings[c % len(rings)]."""
     arr = (C.c_void_p * nranks)()
     dl = None if devlist is None else (C.c_int * nranks)(*devlist)
-    _check(_lib.vcclCommInitAll(arr, int(nranks), dl), "vcclCommInitAll")
+    if rings is None:
+        _check(_lib.vcclCommInitAll(arr, int(nranks), dl), "vcclCommInitAll")
+    else:
+        flat = [int(r) for row in rings for r in row]
+        if len(flat) != len(rings) * nranks:
+            raise ValueError("every ring order lists nranks ranks")
+        _check(_lib.vcclCommInitAllRings(arr, int(nranks), dl, len(rings), (C.c_int * len(flat))(*flat)),
+               "vcclCommInitAllRings")
     _live.update(arr[i] for i in range(nranks))
     return [C.c_void_p(arr[i]) for i in range(nranks)]
+
+
+def vcclCommGetRings(comm) -> list:
+    """The set's ring orders: a list of rows, row k the ranks of ring k in order."""
+    n = vcclCommCount(comm)
+    k = C.c_int()
+    _check(_lib.vcclCommGetRings(comm, C.byref(k), None), "vcclCommGetRings")
+    arr = (C.c_int * (k.value * n))()
+    _check(_lib.vcclCommGetRings(comm, C.byref(k), arr), "vcclCommGetRings")
+    return [list(arr[i * n:(i + 1) * n]) for i in range(k.value)]
 
 
 def vcclCommDestroy(comm):

@@ -908,7 +908,29 @@ __device__ __forceinline__ uint64_t connId(const Ctx& c, int receiver, int kind)
 __device__ __forceinline__ char* fifoOf(const Ctx& c, int proto, int receiver, int kind, uint64_t fifoBytes) {
   const uint64_t lr = (uint64_t)c.lane * c.nranks + receiver;
   if (kind == 0) return c.comm->fifo[proto] + lr * fifoBytes;
+  if (kind > NTREE_CONN) {  // ring k >= 1: its own block of lanes x ranks connections
+    const uint64_t k = (uint64_t)(kind - NTREE_CONN);
+    return c.comm->fifo[proto] + (k * (uint64_t)c.comm->maxLanes * c.nranks + lr) * fifoBytes;
+  }
   return c.comm->treeFifo[proto] + (lr * NTREE_CONN + (kind - 1)) * fifoBytes;
+}
+
+// A channel's ring order (Section II-C): position of a rank, rank at a
+// position (any integer, taken mod R).
+struct RingView {
+  const int8_t* rank;
+  int q;     // this rank's position
+  int R;
+  int kind;  // connection kind of the ring's connections
+  __device__ __forceinline__ int at(int k) const { return (int)rank[((k % R) + R) % R]; }
+};
+__device__ __forceinline__ RingView ringOf(const Ctx& c, const WorkItem& w) {
+  RingView v;
+  v.rank = c.comm->ringRank[w.ring];
+  v.q = (int)uniform((uint32_t)(int32_t)c.comm->ringPos[w.ring][c.rank]);
+  v.R = c.nranks;
+  v.kind = ringKind(w.ring);
+  return v;
 }
 
 // Thread 0 reads the step counters (a receiver's own head, a sender's own
@@ -956,13 +978,14 @@ __device__ __forceinline__ uint64_t roundUp(uint64_t a, uint64_t b) { return cei
 // ------------------------------------------------------------------ algorithms
 
 // Ring AllReduce, Section V-E table: step 0 send, 1..k-2 recvReduceSend,
-// k-1 recvReduceCopySend, k..2k-3 recvCopySend, 2k-2 recv.  At step t rank p
-// works on segment (p - 1 - t) mod k of the loop.
+// k-1 recvReduceCopySend, k..2k-3 recvCopySend, 2k-2 recv.  At step t the
+// rank at ring position q works on segment (q - 1 - t) mod k of the loop.
 template <int PROTO, int SC, int DT, int OP>
 __device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
-  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  const RingView ring = ringOf(c, w);
+  const int R = c.nranks, me = c.rank, q = ring.q, nxt = ring.at(q + 1);
   Conn r[3], s[3];
-  const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
+  const int rk[3] = {ring.kind, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {ring.kind, -1, -1};
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, A = 16 / E, K = w.chunk;
   const uint64_t loopCount = (uint64_t)R * K;
@@ -977,7 +1000,7 @@ __device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
     const uint64_t Kl = (l < full) ? K : roundUp(ceilDiv(rem, R), A);
     const uint64_t lim = (l < full) ? loopCount : rem;
     for (int t = 0; t < 2 * R - 1; ++t) {
-      const int sidx = ((me - 1 - t) % R + 2 * R) % R;
+      const int sidx = ((q - 1 - t) % R + 2 * R) % R;
       const uint64_t a0 = umin(lim, (uint64_t)sidx * Kl), b0 = umin(lim, (uint64_t)(sidx + 1) * Kl);
       const uint64_t off = (w.chOffset + base + a0) * E;
       StepArgs a{};
@@ -1014,12 +1037,14 @@ __device__ void ringAllReduce(const Ctx& c, const WorkItem& w, const CollArgs& a
 }
 
 // Ring ReduceScatter, Section V-E table: step 0 send, 1..k-2 recvReduceSend,
-// k-1 recvReduceCopy; at step t rank p works on block (p - 1 - t) mod k.
+// k-1 recvReduceCopy; at step t the rank at ring position q works on the
+// block of the rank at position (q - 1 - t) mod k.
 template <int PROTO, int SC, int DT, int OP>
 __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
-  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  const RingView ring = ringOf(c, w);
+  const int R = c.nranks, me = c.rank, q = ring.q, nxt = ring.at(q + 1);
   Conn r[3], s[3];
-  const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
+  const int rk[3] = {ring.kind, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {ring.kind, -1, -1};
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, n = w.count, K = w.chunk;
   const char* sendb = uniformPtr(args.send[me]);
@@ -1027,7 +1052,7 @@ __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArg
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
     const uint64_t len = umin(K, w.chCount - a0);
     for (int t = 0; t < R; ++t) {
-      const int blk = ((me - 1 - t) % R + 2 * R) % R;
+      const int blk = ring.at(q - 1 - t);
       StepArgs a{};
       a.nbytes = len * E;
       a.src = sendb + ((uint64_t)blk * n + w.chOffset + a0) * E;
@@ -1044,9 +1069,10 @@ __device__ void ringReduceScatter(const Ctx& c, const WorkItem& w, const CollArg
 // Units are bytes.
 template <int PROTO, int SC, int DT, int OP>
 __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
-  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
+  const RingView ring = ringOf(c, w);
+  const int R = c.nranks, me = c.rank, q = ring.q, nxt = ring.at(q + 1);
   Conn r[3], s[3];
-  const int rk[3] = {0, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {0, -1, -1};
+  const int rk[3] = {ring.kind, -1, -1}, sp[3] = {nxt, -1, -1}, sk[3] = {ring.kind, -1, -1};
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t n = w.count, K = w.chunk;
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
@@ -1056,7 +1082,7 @@ __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& a
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {
     const uint64_t len = umin(K, w.chCount - a0);
     for (int t = 0; t < R; ++t) {
-      const int blk = ((me - t) % R + R) % R;
+      const int blk = ring.at(q - t);
       const uint64_t off = (uint64_t)blk * n + w.chOffset + a0;
       StepArgs a{};
       a.nbytes = len;
@@ -1081,7 +1107,7 @@ __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& a
   }
 }
 
-// Ring Broadcast, Section V-E table: a chain root -> root+1 -> ... -> root-1;
+// Ring Broadcast, Section V-E table: a chain along the ring from the root;
 // root copySend (send in place), middle recvCopySend, last recv.  Bytes.
 // With direct sends the root's copySend would be the chain's slowest stage
 // (a read and two writes per byte, against a read and a write for a middle
@@ -1090,10 +1116,12 @@ __device__ void ringAllGather(const Ctx& c, const WorkItem& w, const CollArgs& a
 // last rank, which otherwise only waits, makes it.
 template <int PROTO, int SC, int DT, int OP>
 __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
-  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
-  const int pos = ((me - w.root) % R + R) % R;
+  const RingView ring = ringOf(c, w);
+  const int R = c.nranks, me = c.rank, nxt = ring.at(ring.q + 1);
+  const int pos = ((ring.q - (int)c.comm->ringPos[w.ring][w.root]) % R + R) % R;
   Conn r[3], s[3];
-  const int rk[3] = {pos > 0 ? 0 : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1}, sk[3] = {0, -1, -1};
+  const int rk[3] = {pos > 0 ? ring.kind : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1},
+            sk[3] = {ring.kind, -1, -1};
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t K = w.chunk;
   const bool direct = (PROTO == PROTO_SIMPLE) && w.direct;
@@ -1126,14 +1154,17 @@ __device__ void ringBroadcast(const Ctx& c, const WorkItem& w, const CollArgs& a
   }
 }
 
-// Ring Reduce, Section V-E table: a chain root+1 -> ... -> root; initiator
-// send, middle recvReduceSend, root recvReduceCopy.
+// Ring Reduce, Section V-E table: a chain along the ring from the root's
+// successor to the root; initiator send, middle recvReduceSend, root
+// recvReduceCopy.
 template <int PROTO, int SC, int DT, int OP>
 __device__ void ringReduce(const Ctx& c, const WorkItem& w, const CollArgs& args, uint64_t* sSteps) {
-  const int R = c.nranks, me = c.rank, nxt = (me + 1) % R;
-  const int pos = ((me - w.root - 1) % R + 2 * R) % R;
+  const RingView ring = ringOf(c, w);
+  const int R = c.nranks, me = c.rank, nxt = ring.at(ring.q + 1);
+  const int pos = ((ring.q - (int)c.comm->ringPos[w.ring][w.root] - 1) % R + 2 * R) % R;
   Conn r[3], s[3];
-  const int rk[3] = {pos > 0 ? 0 : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1}, sk[3] = {0, -1, -1};
+  const int rk[3] = {pos > 0 ? ring.kind : -1, -1, -1}, sp[3] = {pos < R - 1 ? nxt : -1, -1, -1},
+            sk[3] = {ring.kind, -1, -1};
   setupConns<SC>(c, PROTO, r, rk, s, sp, sk, sSteps);
   const uint64_t E = w.elemBytes, K = w.chunk;
   for (uint64_t a0 = 0; a0 < w.chCount; a0 += K) {

@@ -335,8 +335,19 @@ vcclResult_t vcclGetVersion(int* version) {
   return vcclSuccess;
 }
 
-vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist) {
+vcclResult_t vcclCommInitAllRings(vcclComm_t* comms, int nranks, const int* devlist, int nrings, const int* rings) {
   if (!comms || nranks < 2 || nranks > VCCL_MAX_RANKS) return vcclInvalidArgument;
+  if (rings) {
+    if (nrings < 1 || nrings > VCCL_MAX_RINGS) return vcclInvalidArgument;
+    for (int k = 0; k < nrings; ++k) {  // every row a permutation of 0..nranks-1
+      bool seen[VCCL_MAX_RANKS] = {false};
+      for (int q = 0; q < nranks; ++q) {
+        const int r = rings[k * nranks + q];
+        if (r < 0 || r >= nranks || seen[r]) return vcclInvalidArgument;
+        seen[r] = true;
+      }
+    }
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return vcclUnhandledHipError;
   int dev = 0;
@@ -349,14 +360,29 @@ vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist) 
   }
   if (dev < 0 || dev >= ndev) return vcclInvalidArgument;
   Clique* c = nullptr;
-  vcclResult_t r = cliqueCreate(nranks, dev, &c);
+  vcclResult_t r = cliqueCreate(nranks, dev, nrings, rings, &c);
   if (r != vcclSuccess) return r;
   for (int i = 0; i < nranks; ++i) {
     vcclComm* h = new vcclComm{c, i, false};
     c->handles.push_back(h);
     comms[i] = h;
   }
-  logInfo("init %d virtual ranks on device %d, %d channels max", nranks, dev, c->maxLanes);
+  logInfo("init %d virtual ranks on device %d, %d channels max, %d ring order(s)", nranks, dev, c->maxLanes,
+          c->nrings);
+  return vcclSuccess;
+}
+
+vcclResult_t vcclCommInitAll(vcclComm_t* comms, int nranks, const int* devlist) {
+  return vcclCommInitAllRings(comms, nranks, devlist, 0, nullptr);
+}
+
+vcclResult_t vcclCommGetRings(vcclComm_t comm, int* nrings, int* rings) {
+  if (!validHandle(comm) || !nrings) return vcclInvalidArgument;
+  Clique* c = comm->clique;
+  *nrings = c->nrings;
+  if (rings)
+    for (int k = 0; k < c->nrings; ++k)
+      for (int q = 0; q < c->nranks; ++q) rings[k * c->nranks + q] = c->host.ringRank[k][q];
   return vcclSuccess;
 }
 

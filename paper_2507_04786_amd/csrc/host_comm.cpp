@@ -132,9 +132,10 @@ int defaultLaneLimit(int numCUs, int nranks) {
   return std::max(32, std::min(MAX_LANES, (2 * numCUs / nranks) / 8 * 8));
 }
 
-vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
+vcclResult_t cliqueCreate(int nranks, int device, int nrings, const int* rings, Clique** out) {
   Clique* c = new Clique();
   c->nranks = nranks;
+  c->nrings = rings ? nrings : 1;
   c->device = device;
   c->pending.resize(nranks);
   c->p2pSends.resize((size_t)nranks * nranks);
@@ -168,7 +169,8 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
   c->host.treeSlotBytes[PROTO_LL] = TREE_SLOT_BYTES_LL;
   c->host.treeSlotBytes[PROTO_LL128] = TREE_SLOT_BYTES_LL128;
   for (int p = 0; p < 3; ++p) {
-    const uint64_t bytes = (uint64_t)c->maxLanes * nranks * NSLOTS * slot[p];  // ring connections
+    // ring connections, one block of lanes x ranks per ring order
+    const uint64_t bytes = (uint64_t)c->nrings * c->maxLanes * nranks * NSLOTS * slot[p];
     e = hipMalloc((void**)&c->fifo[p], bytes);
     if (e != hipSuccess) return fail(e, "hipMalloc(fifo)");
     if (p != PROTO_SIMPLE) {
@@ -214,6 +216,16 @@ vcclResult_t cliqueCreate(int nranks, int device, Clique** out) {
     c->ranksPerNode = 1;
   }
   buildTrees(nranks, c->ranksPerNode, c->host.parent, c->host.child, c->host.childIdx, c->host.nchild);
+  // ring orders (Section II-C: every channel has its ring, set up once)
+  c->host.nrings = c->nrings;
+  memset(c->host.ringRank, 0, sizeof(c->host.ringRank));
+  memset(c->host.ringPos, 0, sizeof(c->host.ringPos));
+  for (int k = 0; k < c->nrings; ++k)
+    for (int q = 0; q < nranks; ++q) {
+      const int rk = rings ? rings[k * nranks + q] : q;
+      c->host.ringRank[k][q] = (int8_t)rk;
+      c->host.ringPos[k][rk] = (int8_t)q;
+    }
   e = hipMalloc((void**)&c->dcomm, sizeof(DevComm));
   if (e != hipSuccess) return fail(e, "hipMalloc(devcomm)");
   e = hipMemcpy(c->dcomm, &c->host, sizeof(DevComm), hipMemcpyHostToDevice);
@@ -319,7 +331,7 @@ uint64_t cliqueTreeFifoBytes(const Clique* c, int proto) {
 }
 
 uint64_t cliqueRingFifoBytes(const Clique* c, int proto) {
-  return (uint64_t)c->maxLanes * c->nranks * NSLOTS * c->host.slotBytes[proto];
+  return (uint64_t)c->nrings * c->maxLanes * c->nranks * NSLOTS * c->host.slotBytes[proto];
 }
 
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps) {

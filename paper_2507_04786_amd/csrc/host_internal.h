@@ -119,6 +119,7 @@ struct Clique {
   bool treeSplit = true;          // split Simple tree channels into concurrent halves
   int ranksPerNode = 1;           // tree topology: chains of this many ranks, trees across them
   bool ll128 = true;              // LL128 may be planned (its tear test passed on this device)
+  int nrings = 1;                 // ring orders (host.ringRank / host.ringPos); channel c follows c % nrings
   uint64_t* claim = nullptr;  // per-XCD role counters (device)
   uint64_t claimBase = 0;     // role claims of all launches so far, per XCD
 };
@@ -127,7 +128,9 @@ Clique* cliqueOf(vcclComm_t comm);
 int rankOf(vcclComm_t comm);
 
 // host_comm.cpp
-vcclResult_t cliqueCreate(int nranks, int device, Clique** out);
+// rings: nrings rows of nranks ranks (ring orders, validated by the caller), or
+// null for the identity ring
+vcclResult_t cliqueCreate(int nranks, int device, int nrings, const int* rings, Clique** out);
 int defaultLaneLimit(int numCUs, int nranks);
 void cliqueFree(Clique* c);
 vcclResult_t cliqueEnsureTreeFifos(Clique* c, int proto);

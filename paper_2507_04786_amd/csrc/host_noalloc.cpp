@@ -103,6 +103,11 @@ extern "C" vcclResult_t vcclAllReduceNoAlloc(const void* const* sendbuffs, void*
   dc.claim = (uint64_t*)(nd.base + NA_OFF_CLAIM);
   memset(dc.parent, -1, sizeof(dc.parent));
   memset(dc.child, -1, sizeof(dc.child));
+  dc.nrings = 1;  // the identity ring
+  for (int q = 0; q < R; ++q) {
+    dc.ringRank[0][q] = (int8_t)q;
+    dc.ringPos[0][q] = (int8_t)q;
+  }
 
   // the connections this launch uses: (lane * R + receiver) for lane < C
   const uint64_t conns = (uint64_t)C * R;

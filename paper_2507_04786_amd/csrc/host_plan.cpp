@@ -247,6 +247,9 @@ void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t arg
     w.op = copy ? OP_COPY : (uint8_t)(coll.op == vcclMax ? OP_MAX : OP_SUM);
     w.direct = (uint8_t)plan.direct;
     w.tree = (uint8_t)(ch % 2);
+    // ring collectives: channel ch follows ring ch % nrings wherever (on
+    // whichever lane) it runs, so grouping keeps the per-call bits
+    w.ring = (uint8_t)(plan.algo == ALGO_RING && coll.coll != COLL_SENDRECV ? ch % c->nrings : 0);
     w.peer = (uint8_t)coll.peer;
     w.root = coll.root;
     w.argsIndex = argsIndex;
@@ -259,7 +262,6 @@ void fillItems(const Clique* c, const Coll& coll, const Plan& plan, uint32_t arg
     w.chunk = plan.chunkBytes / ub;
     items->push_back(w);
   }
-  (void)c;
 }
 
 // Rough time (us) of one work item, used to balance lanes in grouped launches.

@@ -2,16 +2,18 @@
 //
 // Memory layout in HBM (one communicator set, "clique"):
 //   * FIFOs: for every protocol p, one region for the ring connections,
-//       maxLanes * nranks connections of NSLOTS slots * slotBytes[p] each
-//       (index lane * nranks + receivingRank), and one for the tree
+//       nrings * maxLanes * nranks connections of NSLOTS slots * slotBytes[p]
+//       each (index (ring * maxLanes + lane) * nranks + receivingRank), and
+//       one for the tree
 //       connections (6 per lane and rank, index (lane * nranks + rank) * 6 +
 //       kind - 1, slots of treeSlotBytes[p]), allocated on the first tree
 //       launch under protocol p.
 //     Connection id = (lane * nranks + receivingRank) * NCONN + kind, where kind
-//       0      ring: from the ring predecessor
+//       0      ring 0: from the receiver's predecessor on ring 0
 //       1, 2   tree 0: upward from the receiver's first / second child
 //       3      tree 0: downward from the receiver's parent
-//       4..6   the same three for tree 1.
+//       4..6   the same three for tree 1
+//       7..9   rings 1..3: from the receiver's predecessor on that ring.
 //     A FIFO lives with its receiver (the sender stores into it).
 //   * Counters: one 256-byte record per connection; `tail` (steps published by
 //     the sender) at byte 0 and `head` (steps consumed by the receiver) at byte
@@ -32,7 +34,12 @@ enum : uint8_t { OP_SUM = 0, OP_MAX = 1, OP_COPY = 2 };
 
 constexpr int NSLOTS = 8;
 constexpr int NTREE_CONN = 6;   // tree connection kinds 1..6
-constexpr int NCONN = 1 + NTREE_CONN;
+// Ring orders of a set (Section II-C: each channel has its ring, fixed at
+// initialisation): channel c of a ring collective follows ring c % nrings.
+constexpr int MAX_RINGS = 4;
+constexpr int NCONN = 1 + NTREE_CONN + (MAX_RINGS - 1);
+// connection kind of ring k's connections
+__host__ __device__ constexpr int ringKind(int k) { return k == 0 ? 0 : NTREE_CONN + k; }
 constexpr int MAX_RANKS = 16;
 constexpr int MAX_LANES = 64;
 constexpr int MAX_INLINE = 32;
@@ -84,6 +91,9 @@ struct DevComm {
   int8_t child[2][MAX_RANKS][2];
   int8_t childIdx[2][MAX_RANKS];  // my position among my parent's children
   int8_t nchild[2][MAX_RANKS];
+  int32_t nrings;                   // ring orders, 1..MAX_RINGS
+  int8_t ringRank[MAX_RINGS][MAX_RANKS];  // the rank at each position of ring k
+  int8_t ringPos[MAX_RINGS][MAX_RANKS];   // the position of each rank on ring k
 };
 
 // One channel-slice of one collective, run by one lane (one workgroup per rank).
@@ -98,7 +108,7 @@ struct WorkItem {
   uint8_t scope;             // SCOPE_DEVICE or SCOPE_XCD: store policy of this item's traffic
   uint8_t role;              // tree: ROLE_FUSED, or the up / down half of a split channel, or idle
   uint8_t connLane;          // tree halves: the lane whose connections both halves use
-  uint8_t pad;
+  uint8_t ring;              // ring collectives: the ring order the channel follows
   uint64_t count;            // units per rank (per block for AllGather / ReduceScatter)
   uint64_t chOffset;         // workOffset of this channel, units
   uint64_t chCount;          // channelCount, units
@@ -189,7 +199,7 @@ constexpr uint64_t NA_OFF_WORDS = 1024;  // abort word at +0, error word at +128
 constexpr uint64_t NA_OFF_CLAIM = 2048;  // 8 counters, CLAIM_STRIDE_U64 apart
 constexpr uint64_t NA_OFF_CTR = 4096;
 constexpr uint64_t NA_CTR_BYTES = NA_CONNS * NCONN * CTR_RECORD_U64 * 8;
-constexpr uint64_t NA_OFF_FIFO_SIMPLE = 256u * 1024u;
+constexpr uint64_t NA_OFF_FIFO_SIMPLE = 512u * 1024u;
 constexpr uint64_t NA_OFF_FIFO_LL = NA_OFF_FIFO_SIMPLE + NA_CONNS * NSLOTS * NA_SLOT_SIMPLE;
 constexpr uint64_t NA_SCRATCH_BYTES = NA_OFF_FIFO_LL + NA_CONNS * NSLOTS * NA_SLOT_LL;
 static_assert(sizeof(DevComm) <= NA_OFF_WORDS - NA_OFF_COMM, "DevComm fits its scratch slot");

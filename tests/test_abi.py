@@ -72,3 +72,24 @@ def test_c_client_builds_against_the_header(tmp_path):
     out = tmp_path / "c_client"
     cb.build(str(out))
     assert out.exists() and os.access(str(out), os.X_OK)
+
+
+def test_init_rejects_bad_ring_orders():
+    """Ring orders are checked before the device is touched: every row must
+    be a permutation of the ranks, and there are 1..VCCL_MAX_RINGS rows."""
+    import ctypes as C
+    import paper_2507_04786_amd as vccl
+    lib = vccl.lib()
+    arr = (C.c_void_p * 4)()
+    for rows in ([[0, 1, 1, 3]], [[0, 1, 2, 4]], [[0, 1, 2, -1]], [[0, 1, 2, 3]] * 5):
+        flat = [r for row in rows for r in row]
+        res = lib.vcclCommInitAllRings(arr, 4, None, len(rows), (C.c_int * len(flat))(*flat))
+        assert res == vccl.vcclInvalidArgument, rows
+    flat = (C.c_int * 4)(0, 1, 2, 3)
+    assert lib.vcclCommInitAllRings(arr, 4, None, 0, flat) == vccl.vcclInvalidArgument
+    try:
+        vccl.vcclCommInitAll(4, rings=[[0, 1, 2]])
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("expected a ValueError for a short ring")
