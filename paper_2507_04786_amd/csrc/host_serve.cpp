@@ -351,15 +351,19 @@ vcclResult_t vcclServeSubmit(vcclServer_t s, const vcclRequest_t* req, uint64_t*
   // lanes its plan asks for
   // A request keeps its per-call plan's channels (up to the server's lanes)
   // when it is at least fullPlanBytes large, so it is served as fast as the
-  // same call launched alone, or when it is a floating-point sum
-  // AllReduce, the one collective whose bits depend on the channel count
-  // (the ring's segments and the tree's per-channel trees follow it), so it
-  // gives the per-call bits.  Every other request takes at most
-  // maxLanesPerReq lanes, so that several overlap; their results do not
-  // depend on the channel count.  The cap depends only on the request.
+  // same call launched alone, or when its bits depend on the channel count,
+  // so it gives the per-call bits: a floating-point sum AllReduce (the
+  // ring's segments and the tree's per-channel trees follow the channels),
+  // and, on a set with more than one ring order, a floating-point sum
+  // ReduceScatter or Reduce (each channel folds along its own ring).  Every
+  // other request takes at most maxLanesPerReq lanes, so that several
+  // overlap; their results do not depend on the channel count.  The cap
+  // depends only on the request.
   const Plan full = q->plan;
   const bool large = collSizeBytes((uint8_t)req->coll, req->count, req->datatype, R) >= s->fullPlanBytes;
-  const bool channelBits = req->coll == COLL_ALLREDUCE && req->op == vcclSum && req->datatype != vcclInt32;
+  const bool floatSum = req->op == vcclSum && req->datatype != vcclInt32;
+  const bool channelBits = floatSum && (req->coll == COLL_ALLREDUCE ||
+                                        (c->nrings > 1 && (req->coll == COLL_REDUCESCATTER || req->coll == COLL_REDUCE)));
   q->plan.nchannels = std::min(full.nchannels, (large || channelBits) ? s->L : s->maxLanesPerReq);
   q->bytes = requestBytes(c, *req, q->plan);
   if (q->bytes > s->budget / 2) {

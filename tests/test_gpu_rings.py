@@ -181,3 +181,43 @@ def test_served_requests_on_rings(vccl, ring_set):
     if plan["algo"] == vccl.vcclAlgoRing:
         want = folds.ring_allreduce(xs, "sum", "float32", plan["nchannels"], plan["chunkBytes"] // 4, rings=rings)
         _same(got[0], want, "served vs the fold on its rings")
+
+
+def test_served_reducescatter_and_reduce_keep_per_call_bits_on_rings(vccl, ring_set):
+    """On a set with several ring orders a float sum ReduceScatter or Reduce
+    folds each channel along its own ring, so the server keeps its per-call
+    channel count (where one ring would let it take fewer lanes)."""
+    import time
+    R = 8
+    comms, rings = ring_set(R, 3)
+    cases = []
+    for coll, n, root in (("reducescatter", 1 << 17, 0), ("reduce", 1 << 19, 5)):
+        xs = _inputs(R, "float32", H.send_len(coll, n, R), extra=len(cases) + 90)
+        per = _run(vccl, comms, coll, xs, n, "float32", root)
+        cases.append((coll, n, root, xs, per, vccl.vcclCommGetLastPlan(comms[0])))
+    srv = vccl.vcclServeCreate(comms, 1 << 30, 64)  # the set's lane limit: every per-call plan fits
+    outs = []
+    try:
+        for coll, n, root, xs, per, plan in cases:
+            sends = [H.to_dev(x) for x in xs]
+            recvs = [H.empty_dev(H.recv_len(coll, n, R), "float32") for _ in range(R)]
+            H.torch().cuda.synchronize()
+            code = {"reducescatter": 4, "reduce": 2}[coll]
+            rid = vccl.vcclServeSubmit(srv, code, vccl.vcclFloat32, vccl.vcclSum, root, n, sends, recvs)
+            sp = vccl.vcclServeGetPlan(srv, rid)
+            deadline = time.time() + 30
+            while True:
+                done, status, _ = vccl.vcclServeTest(srv, rid)
+                if done:
+                    assert status == vccl.vcclSuccess
+                    break
+                assert time.time() < deadline, "request did not complete"
+            outs.append(([H.from_dev(r, "float32") for r in recvs], sp))
+    finally:
+        vccl.vcclServeDestroy(srv)
+    for (coll, n, root, xs, per, plan), (got, sp) in zip(cases, outs):
+        assert sp["nchannels"] == plan["nchannels"], (coll, sp, plan)
+        for r in range(R):
+            if coll == "reduce" and r != root:
+                continue
+            _same(got[r], per[r], f"served {coll} vs per-call rank {r}")
