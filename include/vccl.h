@@ -282,7 +282,10 @@ vcclResult_t vcclCommGetLastTimestamps(vcclComm_t comm, uint64_t* stamps_ns, int
  * reported plan.  The first call on a device looks the array up with that
  * device current; every call then enqueues two launches on `stream` (one
  * that rewrites the descriptor and zeroes the counters and LL slots it
- * uses, then the collective), and calls nothing that allocates.  All calls
+ * uses, then the collective), and calls nothing that allocates.  Both
+ * launches may be captured in a HIP graph (call once outside capture first,
+ * so the array is looked up): the clearing is a kernel, not a memset, so every
+ * replay starts afresh like a call.  All calls
  * on one device share its array: calls that overlap on that device (other
  * streams, other threads) race and must not be made.  Every wait is bounded
  * (5 s); a wait that runs out leaves the output undefined and is not

@@ -97,3 +97,37 @@ def test_no_alloc_rejects_bad_arguments(vccl):
     assert e.value.code == vccl.vcclInvalidArgument
     # nothing is enqueued for an empty call
     assert vccl.vcclAllReduceNoAlloc(x[:4], x[:4], 0, vccl.vcclFloat32, vccl.vcclSum)["nchannels"] == 0
+
+
+def test_no_alloc_graph_capture_replays(vccl):
+    """The allocation-free AllReduce captured in a HIP graph: each replay
+    clears the scratch state it uses with a kernel (no memset node), so every
+    replay, with eager work and other allocation-free calls between replays,
+    gives the eager result."""
+    t = H.torch()
+    for R, n, dtype in ((8, 1 << 20, "float32"), (4, 4099, "bfloat16"), (16, 8, "float32")):
+        print(f"no-alloc graph capture: R={R} n={n} {dtype}", flush=True)
+        xs = si.rank_inputs(si.WL_RING_AR_SWEEP, R, dtype, n, extra=40 + R)
+        sends = [H.to_dev(x) for x in xs]
+        recvs = [H.empty_dev(n, dtype) for _ in range(R)]
+        code = vccl.DTYPE_NAMES[dtype]
+        plan = vccl.vcclAllReduceNoAlloc(sends, recvs, n, code, vccl.vcclSum)
+        t.cuda.synchronize()
+        ref = [H.from_dev(r, dtype).copy() for r in recvs]
+        want = folds.ring_allreduce(xs, "sum", dtype, plan["nchannels"], plan["chunkBytes"] // H.ELEM[dtype])
+        assert ref[0].tobytes() == want.tobytes()
+        graph = t.cuda.CUDAGraph()
+        with t.cuda.graph(graph):
+            vccl.vcclAllReduceNoAlloc(sends, recvs, n, code, vccl.vcclSum, stream=t.cuda.current_stream())
+        other = [t.randn(999, device="cuda") for _ in range(R)]
+        oout = [t.empty(999, device="cuda") for _ in range(R)]
+        for rep in range(4):
+            for r in recvs:
+                r.fill_(0x5A)
+            vccl.vcclAllReduceNoAlloc(other, oout, 999, vccl.vcclFloat32, vccl.vcclSum)
+            t.cuda.synchronize()
+            graph.replay()
+            t.cuda.synchronize()
+            for r in range(R):
+                assert H.from_dev(recvs[r], dtype).tobytes() == ref[r].tobytes(), (R, n, rep, r)
+        del graph
