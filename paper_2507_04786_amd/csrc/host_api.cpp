@@ -182,9 +182,10 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
     c->stageNext ^= 1;
     VCCL_HIPCHECK(hipEventSynchronize(c->stageEvent[k]));
     char* stage = (char*)c->hStage[k];
+    const WorkLayout wl = workLayout(items.size());
     WorkItem* sItems = (WorkItem*)stage;
-    uint32_t* sLane = (uint32_t*)(stage + items.size() * sizeof(WorkItem));
-    CollArgs* sArgs = (CollArgs*)(stage + items.size() * sizeof(WorkItem) + (MAX_LANES + 1) * sizeof(uint32_t));
+    uint32_t* sLane = (uint32_t*)(stage + wl.laneOff);
+    CollArgs* sArgs = (CollArgs*)(stage + wl.argsOff);
     uint32_t pos = 0;
     for (int l = 0; l < nlanes; ++l) {
       sLane[l] = pos;
@@ -194,13 +195,13 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
     for (size_t g = 0; g < colls.size(); ++g) sArgs[g] = colls[g].args;
     hipStream_t ls = ss.list[ss.n - 1];
     VCCL_HIPCHECK(hipStreamWaitEvent(ls, c->lastLaunchDone, 0));
-    VCCL_HIPCHECK(hipMemcpyAsync(c->dItems, sItems, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, ls));
-    VCCL_HIPCHECK(hipMemcpyAsync(c->dLaneStart, sLane, (nlanes + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, ls));
-    VCCL_HIPCHECK(hipMemcpyAsync(c->dArgs, sArgs, colls.size() * sizeof(CollArgs), hipMemcpyHostToDevice, ls));
+    // one copy of the whole list (items, lane starts, pointer tables)
+    VCCL_HIPCHECK(hipMemcpyAsync(c->dWork, stage, wl.argsOff + colls.size() * sizeof(CollArgs),
+                                 hipMemcpyHostToDevice, ls));
     VCCL_HIPCHECK(hipEventRecord(c->stageEvent[k], ls));
-    d.items = c->dItems;
-    d.laneStart = c->dLaneStart;
-    d.args = c->dArgs;
+    d.items = (const WorkItem*)c->dWork;
+    d.laneStart = (const uint32_t*)(c->dWork + wl.laneOff);
+    d.args = (const CollArgs*)(c->dWork + wl.argsOff);
     d.stamps = c->dStamps;
     nitems = items.size();
   }

@@ -292,9 +292,7 @@ void cliqueFree(Clique* c) {
   if (c->ctr) hipFree(c->ctr);
   if (c->claim) hipFree(c->claim);
   if (c->dcomm) hipFree(c->dcomm);
-  if (c->dItems) hipFree(c->dItems);
-  if (c->dLaneStart) hipFree(c->dLaneStart);
-  if (c->dArgs) hipFree(c->dArgs);
+  if (c->dWork) hipFree(c->dWork);
   if (c->dStamps) hipFree(c->dStamps);
   if (c->dProfile) hipFree(c->dProfile);
   for (int i = 0; i < 2; ++i) {
@@ -334,37 +332,35 @@ uint64_t cliqueRingFifoBytes(const Clique* c, int proto) {
   return (uint64_t)c->nrings * c->maxLanes * c->nranks * NSLOTS * c->host.slotBytes[proto];
 }
 
+WorkLayout workLayout(size_t items) {
+  WorkLayout w;
+  w.laneOff = (items * sizeof(WorkItem) + 255) / 256 * 256;
+  w.argsOff = w.laneOff + ((MAX_LANES + 1) * sizeof(uint32_t) + 255) / 256 * 256;
+  return w;
+}
+
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps) {
-  if (items > c->itemCap) {
-    size_t cap = items < 256 ? 256 : items * 2;
-    if (c->dItems) {
+  if (items > c->itemCap || args > c->argCap) {
+    const size_t icap = items > c->itemCap ? (items < 256 ? 256 : items * 2) : c->itemCap;
+    const size_t acap = args > c->argCap ? (args < 128 ? 128 : args * 2) : c->argCap;
+    const size_t bytes = workLayout(icap).argsOff + acap * sizeof(CollArgs);
+    if (c->dWork) {
       VCCL_HIPCHECK(hipDeviceSynchronize());
-      VCCL_HIPCHECK(hipFree(c->dItems));
-      VCCL_HIPCHECK(hipFree(c->dLaneStart));
+      VCCL_HIPCHECK(hipFree(c->dWork));
+      c->dWork = nullptr;
     }
-    VCCL_HIPCHECK(hipMalloc((void**)&c->dItems, cap * sizeof(WorkItem)));
-    VCCL_HIPCHECK(hipMalloc((void**)&c->dLaneStart, (MAX_LANES + 1) * sizeof(uint32_t)));
-    c->itemCap = cap;
-  }
-  if (args > c->argCap) {
-    size_t cap = args < 128 ? 128 : args * 2;
-    if (c->dArgs) {
-      VCCL_HIPCHECK(hipDeviceSynchronize());
-      VCCL_HIPCHECK(hipFree(c->dArgs));
-    }
-    VCCL_HIPCHECK(hipMalloc((void**)&c->dArgs, cap * sizeof(CollArgs)));
-    c->argCap = cap;
-  }
-  const size_t stage = c->itemCap * sizeof(WorkItem) + (MAX_LANES + 1) * sizeof(uint32_t) + c->argCap * sizeof(CollArgs);
-  if (stage > c->stageCap) {
+    VCCL_HIPCHECK(hipMalloc((void**)&c->dWork, bytes));
     for (int i = 0; i < 2; ++i) {
       if (c->hStage[i]) {
         VCCL_HIPCHECK(hipEventSynchronize(c->stageEvent[i]));
         VCCL_HIPCHECK(hipHostFree(c->hStage[i]));
+        c->hStage[i] = nullptr;
       }
-      VCCL_HIPCHECK(hipHostMalloc(&c->hStage[i], stage, 0));
+      VCCL_HIPCHECK(hipHostMalloc(&c->hStage[i], bytes, 0));
     }
-    c->stageCap = stage;
+    c->itemCap = icap;
+    c->argCap = acap;
+    c->stageCap = bytes;
   }
   if (stamps > c->stampCap) {
     size_t cap = stamps < 1024 ? 1024 : stamps * 2;

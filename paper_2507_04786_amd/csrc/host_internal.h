@@ -84,9 +84,10 @@ struct Clique {
   uint32_t* hAbort = nullptr; // pinned
   uint32_t* hError = nullptr; // pinned
   // group / work-list staging
-  WorkItem* dItems = nullptr;
-  uint32_t* dLaneStart = nullptr;
-  CollArgs* dArgs = nullptr;
+  // a grouped launch's work list: items, lane starts and pointer tables in
+  // one device buffer, laid out as workLayout gives, filled from a pinned
+  // staging copy of the same layout by one copy
+  char* dWork = nullptr;
   size_t itemCap = 0, argCap = 0;
   void* hStage[2] = {nullptr, nullptr};
   size_t stageCap = 0;
@@ -137,6 +138,12 @@ vcclResult_t cliqueEnsureTreeFifos(Clique* c, int proto);
 uint64_t cliqueTreeFifoBytes(const Clique* c, int proto);
 uint64_t cliqueRingFifoBytes(const Clique* c, int proto);
 vcclResult_t cliqueEnsureWorkCapacity(Clique* c, size_t items, size_t args, size_t stamps);
+// Work-list layout for `items` items: byte offsets of the lane starts and of
+// the pointer tables, each 256-byte aligned after the items
+struct WorkLayout {
+  size_t laneOff, argsOff;
+};
+WorkLayout workLayout(size_t items);
 int cliqueOccupancy(Clique* c, int nthreads);
 void buildTrees(int nranks, int ranksPerNode, int8_t parent[2][MAX_RANKS], int8_t child[2][MAX_RANKS][2],
                 int8_t childIdx[2][MAX_RANKS], int8_t nchild[2][MAX_RANKS]);
