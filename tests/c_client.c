@@ -2,11 +2,13 @@
  * (include/vccl.h) and the HIP runtime's C API: R virtual ranks on the
  * current device.
  *
- *   c_client [R [n [keep]]]
+ *   c_client [R [n [keep | rings]]]
  *
  * With "keep" the program exits without destroying its communicators or
  * freeing its buffers, leaving the set's device memory, pinned host words
- * and events to process exit.
+ * and events to process exit.  With "rings" the set is created with two
+ * ring orders (the reversed ring and a rotation of it by two), read back
+ * with vcclCommGetRings; every check below then runs on them.
  *
  * Checks, on int32 data whose results are exact in any summation order:
  *   - AllReduce sum: recv_r[i] = sum over ranks q of x_q[i];
@@ -79,12 +81,28 @@ int main(int argc, char** argv) {
   const int R = argc > 1 ? atoi(argv[1]) : 4;
   const size_t n = argc > 2 ? (size_t)strtoull(argv[2], NULL, 10) : 100003;
   const int keep = argc > 3 && strcmp(argv[3], "keep") == 0;
+  const int useRings = argc > 3 && strcmp(argv[3], "rings") == 0;
   if (R < 2 || R > MAXR || n == 0) {
     fprintf(stderr, "usage: c_client [R in 2..%d [n > 0]]\n", MAXR);
     return 1;
   }
   vcclComm_t comms[MAXR];
-  V_OK(vcclCommInitAll(comms, R, NULL));
+  if (useRings) {
+    int rings[2 * MAXR], back[2 * MAXR], nr = 0;
+    for (int q = 0; q < R; ++q) {
+      rings[q] = R - 1 - q;                   /* reversed */
+      rings[R + q] = (R - 1 - q + 2) % R;     /* the reversed ring rotated by two */
+    }
+    V_OK(vcclCommInitAllRings(comms, R, NULL, 2, rings));
+    V_OK(vcclCommGetRings(comms[R - 1], &nr, NULL));
+    V_OK(vcclCommGetRings(comms[R - 1], &nr, back));
+    if (nr != 2 || memcmp(rings, back, (size_t)(2 * R) * sizeof(int)) != 0) {
+      fprintf(stderr, "vcclCommGetRings does not return the rings given\n");
+      ++failures;
+    }
+  } else {
+    V_OK(vcclCommInitAll(comms, R, NULL));
+  }
   hipStream_t st;
   HIP_OK(hipStreamCreate(&st));
 

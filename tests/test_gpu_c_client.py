@@ -42,3 +42,12 @@ def test_exit_with_live_sets_is_clean(client):
     assert res.returncode == 0, f"exit {res.returncode}\n{res.stdout}\n{res.stderr}"
     rec = json.loads([l for l in res.stdout.splitlines() if l.startswith("{")][-1])
     assert rec["ok"] == 1
+
+
+@pytest.mark.parametrize("R,n", [(8, 50021), (5, 777)])
+def test_c_client_on_ring_orders(client, R, n):
+    """The same checks on a set created from C with two ring orders."""
+    res = subprocess.run([client, str(R), str(n), "rings"], capture_output=True, text=True, timeout=90)
+    assert res.returncode == 0, f"exit {res.returncode}\n{res.stdout}\n{res.stderr}"
+    rec = json.loads([l for l in res.stdout.splitlines() if l.startswith("{")][-1])
+    assert rec["ok"] == 1 and rec["nranks"] == R
