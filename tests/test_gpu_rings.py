@@ -221,3 +221,41 @@ def test_served_reducescatter_and_reduce_keep_per_call_bits_on_rings(vccl, ring_
             if coll == "reduce" and r != root:
                 continue
             _same(got[r], per[r], f"served {coll} vs per-call rank {r}")
+
+
+@pytest.mark.parametrize("proto", ["simple", "ll"])
+def test_trees_and_transfers_ignore_ring_orders(vccl, ring_set, proto):
+    """Ring orders shape ring collectives only: on a set with three of them a
+    forced tree AllReduce (Section II-C, double binary tree) equals the
+    oracle's tree simulation, and a grouped all-to-all of Send/Recv pairs
+    equals its definition."""
+    from oracle import definitions as defs
+    R, C, n = 8, 3, 20011
+    comms, rings = ring_set(R, 3)
+    xs = _inputs(R, "float32", n, extra=321)
+    H.tune(vccl, comms, "tree", proto, nchannels=C, chunk=4096)
+    try:
+        got = _run(vccl, comms, "allreduce", xs, n, "float32")
+        plan = vccl.vcclCommGetLastPlan(comms[0])
+    finally:
+        H.untune(vccl, comms)
+    assert plan["algo"] == vccl.vcclAlgoTree
+    want = sim.run("allreduce", xs, dtype="float32", nchannels=C, chunk_bytes=plan["chunkBytes"], algo="tree")
+    for r in range(R):
+        _same(got[r], want[r], f"tree {proto} on rings rank {r}")
+    m = 1001
+    ys = si.rank_inputs(si.WL_P2P, R, "int32", R * m, lo=-2**20, hi=2**20, extra=17)
+    sends = [H.to_dev(y) for y in ys]
+    outs = [H.empty_dev(R * m, "int32") for _ in range(R)]
+    H.torch().cuda.synchronize()
+    vccl.vcclGroupStart()
+    for a in range(R):
+        for b in range(R):
+            vccl.vcclSend(sends[a][b * m:(b + 1) * m], m, vccl.vcclInt32, b, comms[a])
+            vccl.vcclRecv(outs[b][a * m:(a + 1) * m], m, vccl.vcclInt32, a, comms[b])
+    vccl.vcclGroupEnd()
+    H.torch().cuda.synchronize()
+    assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+    want = defs.alltoall(ys)
+    for b in range(R):
+        _same(H.from_dev(outs[b], "int32"), want[b], f"all-to-all on rings, rank {b}")
