@@ -1,24 +1,50 @@
-"""Buffers past 4 GiB per rank: offsets, channel partitions (Section V-C) and
-steps must stay 64-bit from the planner to the last store.  Two ranks keep
-the host side small and give every collective a result that holds at any
-size: an fp32 AllReduce, ReduceScatter or Reduce of two ranks is one IEEE
-addition per element (either order gives the same bits), so the whole
-output equals the element-wise sum, and the copies equal their sources.
-For the AllReduce the oracle's fold for the reported plan is also compared
-on sampled elements: random ones, both sides of every channel boundary,
-the elements around the 2 GiB and 4 GiB byte offsets, and the last ones."""
+"""Buffers beyond 4 GiB per rank: 64-bit counts and offsets on every path.
+
+Inputs are a closed-form hash of (rank, index), generated on the device in
+slices, so the expected value at any index is computed on the host from the
+index alone: int32 sums are exact in any order (they wrap mod 2^32), so
+every sampled element of AllReduce and ReduceScatter must equal the sum of
+the hashes, AllGather and Send/Recv must move them unchanged.  Samples
+include the elements around every 4 GiB and 2 GiB byte boundary and the
+tail."""
 import numpy as np
 import pytest
 
-import synthetic_inputs as si
-from oracle import folds
-from oracle import partition as pt
 from tests import gpu_harness as H
 
 pytestmark = pytest.mark.gpu
 
-R = 2
-N_AR = (1 << 30) + 4099      # fp32 elements per rank: 4 GiB + 16 KiB
+A, B = 2654435761, 40503
+SLICE = 1 << 26
+
+
+def f_host(r, i):
+    v = (np.asarray(i, dtype=np.uint64) * np.uint64(A) + np.uint64(r * B)) & np.uint64(0xFFFFFFFF)
+    return v.astype(np.uint32).view(np.int32)
+
+
+def fill_dev(t, buf, r, base=0):
+    """buf[j] = f(r, base + j), computed on the device slice by slice."""
+    n = buf.numel()
+    for s in range(0, n, SLICE):
+        e = min(n, s + SLICE)
+        idx = t.arange(base + s, base + e, dtype=t.int64, device=buf.device)
+        v = (idx * A + r * B) & 0xFFFFFFFF
+        buf[s:e] = t.where(v >= 1 << 31, v - (1 << 32), v).to(t.int32)
+
+
+def samples(n, k=20000, seed=3):
+    rng = np.random.default_rng(seed)
+    edges = []
+    for b in (1 << 29, 1 << 30, 3 << 29, 1 << 31):  # element indices at 2, 4, 6, 8 GiB of int32
+        if b < n:
+            edges += [b - 2, b - 1, b, b + 1]
+    idx = np.concatenate([rng.integers(0, n, k), np.arange(min(n, 64)), np.arange(max(0, n - 64), n), edges])
+    return np.unique(idx[(idx >= 0) & (idx < n)])
+
+
+def at(t, buf, idx):
+    return buf[t.from_numpy(idx.astype(np.int64)).to(buf.device)].cpu().numpy()
 
 
 @pytest.fixture(scope="module")
@@ -27,123 +53,97 @@ def vccl():
     return v
 
 
-def _sample(n, nch, align, seed):
-    rng = np.random.default_rng([0x5EED, 4096, seed])
-    per = pt.round_up(pt.ceil_div(n, nch), align)
-    pts = [rng.integers(0, n, size=1 << 20)]
-    for c in range(1, nch + 1):
-        b = min(n, c * per)
-        pts.append(np.arange(max(0, b - 2), min(n, b + 2)))
-    for byte in (1 << 31, 1 << 32):
-        e = byte // 4
-        pts.append(np.arange(max(0, e - 3), min(n, e + 3)))
-    pts.append(np.arange(n - 8, n))
-    return np.unique(np.concatenate(pts))
-
-
-def test_allreduce_past_4gib(vccl):
+def test_allreduce_over_4gib_per_rank(vccl):
     t = H.torch()
-    print(f"huge AllReduce: {R} ranks, fp32, {N_AR} elements per rank", flush=True)
-    xs = si.rank_inputs(si.WL_RING_AR_SWEEP, R, "float32", N_AR, extra=4096)
+    R, n = 4, (9 << 30) // 8  # 4.5 GiB of int32 per rank
     comms = vccl.vcclCommInitAll(R)
     try:
-        sends = [H.to_dev(x) for x in xs]
-        recvs = [H.empty_dev(N_AR, "float32") for _ in range(R)]
-        H.call(vccl, comms, "allreduce", sends, recvs, N_AR, "float32")
-        t.cuda.synchronize()
-        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
-        plan = vccl.vcclCommGetLastPlan(comms[0])
-        print(f"plan {plan}", flush=True)
-        # every element: one fp32 addition, and both ranks hold the same bits
-        assert bool(t.equal(recvs[0], sends[0] + sends[1]))
-        assert bool(t.equal(recvs[1], recvs[0]))
-        # the oracle's fold for this plan on sampled elements
-        idx = _sample(N_AR, plan["nchannels"], pt.align_units("allreduce", 4), 1)
-        want = folds.ring_allreduce(xs, "sum", "float32", plan["nchannels"], plan["chunkBytes"] // 4, idx=idx)
-        got = recvs[0][t.from_numpy(idx).to("cuda")].cpu().numpy()
-        assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
-    finally:
-        for c in comms:
-            vccl.vcclCommDestroy(c)
-        del xs
-        t.cuda.empty_cache()
-
-
-def test_copies_past_4gib(vccl):
-    """AllGather into 4 GiB + 8 KiB per rank, then Broadcast of 4 GiB +
-    16 KiB from rank 1: bitwise copies of their sources."""
-    t = H.torch()
-    comms = vccl.vcclCommInitAll(R)
-    try:
-        n = (1 << 29) + 1025                       # fp32 elements sent per rank
-        print(f"huge AllGather: {R} ranks, {n} fp32 elements per rank", flush=True)
-        xs = si.rank_inputs(si.WL_TREE_AND_CHAINS, R, "float32", n, extra=4096)
-        sends = [H.to_dev(x) for x in xs]
-        del xs
-        recvs = [H.empty_dev(R * n, "float32") for _ in range(R)]
-        H.call(vccl, comms, "allgather", sends, recvs, n, "float32")
-        t.cuda.synchronize()
-        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
-        print(f"plan {vccl.vcclCommGetLastPlan(comms[0])}", flush=True)
+        bufs = [t.empty(n, dtype=t.int32, device="cuda") for _ in range(2 * R)]
+        sends, recvs = bufs[:R], bufs[R:]
         for r in range(R):
-            for q in range(R):
-                assert bool(t.equal(recvs[r][q * n:(q + 1) * n], sends[q])), (r, q)
-        del sends, recvs
-        t.cuda.empty_cache()
-
-        m = (1 << 30) + 4097                       # fp32 elements broadcast
-        print(f"huge Broadcast: {R} ranks, {m} fp32 elements, root 1", flush=True)
-        xs = si.rank_inputs(si.WL_TREE_AND_CHAINS, R, "float32", m, extra=4097)
-        sends = [H.to_dev(x) for x in xs]
-        del xs
-        recvs = [H.empty_dev(m, "float32") for _ in range(R)]
-        H.call(vccl, comms, "broadcast", sends, recvs, m, "float32", root=1)
-        t.cuda.synchronize()
-        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
-        print(f"plan {vccl.vcclCommGetLastPlan(comms[0])}", flush=True)
-        for r in range(R):
-            assert bool(t.equal(recvs[r], sends[1])), r
-        del sends, recvs
+            fill_dev(t, sends[r], r)
+        idx = samples(n)
+        want = sum(f_host(r, idx).astype(np.int64) for r in range(R))
+        want = (want & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+        for proto in ("auto", "ll"):
+            if proto == "auto":
+                H.untune(vccl, comms)
+            else:
+                H.tune(vccl, comms, "ring", proto, nchannels=32)
+            try:
+                print(f"allreduce 4.5 GiB per rank, {proto}", flush=True)
+                H.call(vccl, comms, "allreduce", sends, recvs, n, "int32")
+                t.cuda.synchronize()
+                assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+            finally:
+                H.untune(vccl, comms)
+            for r in range(R):
+                assert np.array_equal(at(t, recvs[r], idx), want), (proto, r)
+        del bufs, sends, recvs
     finally:
         for c in comms:
             vccl.vcclCommDestroy(c)
         t.cuda.empty_cache()
 
 
-def test_reductions_past_4gib(vccl):
-    """ReduceScatter from 4 GiB + 8 KiB per rank, then Reduce of 4 GiB +
-    16 KiB to rank 0: each output element is one fp32 addition of the two
-    ranks' elements."""
+def test_allgather_and_reducescatter_over_4gib(vccl):
     t = H.torch()
+    R, n = 4, 300 * 1000 * 1000  # blocks of 1.2 GB: 4.8 GB gathered / scattered per rank
     comms = vccl.vcclCommInitAll(R)
     try:
-        n = (1 << 29) + 1029                       # fp32 elements received per rank
-        print(f"huge ReduceScatter: {R} ranks, {R * n} fp32 elements sent per rank", flush=True)
-        xs = si.rank_inputs(si.WL_TREE_AND_CHAINS, R, "float32", R * n, extra=4098)
-        sends = [H.to_dev(x) for x in xs]
-        del xs
-        recvs = [H.empty_dev(n, "float32") for _ in range(R)]
-        H.call(vccl, comms, "reducescatter", sends, recvs, n, "float32")
+        small = [t.empty(n, dtype=t.int32, device="cuda") for _ in range(R)]
+        big = [t.empty(R * n, dtype=t.int32, device="cuda") for _ in range(R)]
+        # AllGather: rank q contributes f(q, i); everyone ends with all blocks
+        for q in range(R):
+            fill_dev(t, small[q], q)
+        print("allgather 4.8 GB per rank", flush=True)
+        H.call(vccl, comms, "allgather", small, big, n, "int32")
         t.cuda.synchronize()
         assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
-        print(f"plan {vccl.vcclCommGetLastPlan(comms[0])}", flush=True)
+        idx = samples(R * n)
+        want = f_host(0, idx % n)
+        for q in range(1, R):
+            sel = idx // n == q
+            want[sel] = f_host(q, idx[sel] % n)
         for r in range(R):
-            assert bool(t.equal(recvs[r], sends[0][r * n:(r + 1) * n] + sends[1][r * n:(r + 1) * n])), r
-        del sends, recvs
+            assert np.array_equal(at(t, big[r], idx), want), ("allgather", r)
+        # ReduceScatter: rank q's input is f(q, j) over R n elements
+        for q in range(R):
+            fill_dev(t, big[q], q)
+        print("reducescatter 4.8 GB per rank", flush=True)
+        H.call(vccl, comms, "reducescatter", big, small, n, "int32")
+        t.cuda.synchronize()
+        assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
+        idx = samples(n)
+        for r in range(R):
+            want = sum(f_host(q, r * n + idx).astype(np.int64) for q in range(R))
+            want = (want & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+            assert np.array_equal(at(t, small[r], idx), want), ("reducescatter", r)
+        del small, big
+    finally:
+        for c in comms:
+            vccl.vcclCommDestroy(c)
         t.cuda.empty_cache()
 
-        m = (1 << 30) + 4101                       # fp32 elements reduced
-        print(f"huge Reduce: {R} ranks, {m} fp32 elements, root 0", flush=True)
-        xs = si.rank_inputs(si.WL_TREE_AND_CHAINS, R, "float32", m, extra=4099)
-        sends = [H.to_dev(x) for x in xs]
-        del xs
-        recvs = [H.empty_dev(m, "float32") for _ in range(R)]
-        H.call(vccl, comms, "reduce", sends, recvs, m, "float32", root=0)
+
+def test_sendrecv_over_4gib(vccl):
+    t = H.torch()
+    R, n = 2, (9 << 30) // 8
+    comms = vccl.vcclCommInitAll(R)
+    try:
+        src = t.empty(n, dtype=t.int32, device="cuda")
+        dst = t.empty(n, dtype=t.int32, device="cuda")
+        fill_dev(t, src, 5)
+        print("send/recv 4.5 GiB", flush=True)
+        vccl.vcclGroupStart()
+        vccl.vcclSend(src, n, vccl.vcclInt32, 1, comms[0])
+        vccl.vcclRecv(dst, n, vccl.vcclInt32, 0, comms[1])
+        vccl.vcclGroupEnd()
         t.cuda.synchronize()
         assert vccl.vcclCommGetAsyncError(comms[0]) == vccl.vcclSuccess
-        print(f"plan {vccl.vcclCommGetLastPlan(comms[0])}", flush=True)
-        assert bool(t.equal(recvs[0], sends[0] + sends[1]))
-        del sends, recvs
+        idx = samples(n)
+        assert np.array_equal(at(t, dst, idx), f_host(5, idx))
+        del src, dst
     finally:
         for c in comms:
             vccl.vcclCommDestroy(c)
