@@ -13,7 +13,9 @@
  * Checks, on int32 data whose results are exact in any summation order:
  *   - AllReduce sum: recv_r[i] = sum over ranks q of x_q[i];
  *   - AllGather and ReduceScatter issued together in one group;
- *   - Broadcast from rank 1.
+ *   - Broadcast from rank 1;
+ *   - the allocation-free AllReduce (no communicator; int32 max) on the same
+ *     buffers, twice, the second call smaller.
  * Then times an 8-byte AllReduce issued from C (R calls, then a stream
  * synchronisation) to show the per-call host cost without an interpreter.
  * Prints one JSON line; exits 0 only when every check passed. */
@@ -168,6 +170,33 @@ int main(int argc, char** argv) {
   for (int q = 0; q < R; ++q) {
     HIP_OK(hipMemcpy(host, recv[q], n * sizeof(int32_t), hipMemcpyDeviceToHost));
     expectEqual("broadcast", host, want, n);
+  }
+
+  /* the allocation-free AllReduce: rank arrays of the same buffers */
+  {
+    const void* sb[MAXR];
+    void* rb[MAXR];
+    for (int q = 0; q < R; ++q) {
+      sb[q] = send[q];
+      rb[q] = recv[q];
+    }
+    const size_t counts[2] = {n, n / 3 + 1};
+    for (int k = 0; k < 2; ++k) {
+      vcclPlanInfo_t plan;
+      V_OK(vcclAllReduceNoAlloc(sb, rb, R, counts[k], vcclInt32, vcclMax, (void*)st, &plan));
+      HIP_OK(hipStreamSynchronize(st));
+      for (size_t i = 0; i < counts[k]; ++i) {
+        int32_t m = value(0, i);
+        for (int q = 1; q < R; ++q)
+          if (value(q, i) > m) m = value(q, i);
+        want[i] = m;
+      }
+      for (int q = 0; q < R; ++q) {
+        HIP_OK(hipMemcpy(host, recv[q], counts[k] * sizeof(int32_t), hipMemcpyDeviceToHost));
+        expectEqual(k ? "allreduce without allocation, second call" : "allreduce without allocation", host, want,
+                    counts[k]);
+      }
+    }
   }
 
   vcclResult_t async = vcclSuccess;
