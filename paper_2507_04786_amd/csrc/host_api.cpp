@@ -66,6 +66,53 @@ vcclResult_t launchPrepared(Clique* c, LaunchDesc& d, int grid, int block, const
   return vcclSuccess;
 }
 
+// A split tree's lanes: channel ch's up half on lane ch, its down half on
+// lane off + ch (off = 8 ceil(C / 8), a multiple of 8, so both halves run on
+// one XCD); lanes between the two groups stay idle.
+void splitTreeLanes(std::vector<WorkItem>* items) {
+  const int C = (int)items->size(), off = 8 * ((C + 7) / 8);
+  std::vector<WorkItem> byLane((size_t)(off + C));
+  for (int l = 0; l < off; ++l) {
+    byLane[l] = (*items)[l < C ? l : 0];
+    byLane[l].role = l < C ? ROLE_UP : ROLE_IDLE;
+    byLane[l].connLane = (uint8_t)l;
+  }
+  for (int ch = 0; ch < C; ++ch) {
+    byLane[off + ch] = (*items)[ch];
+    byLane[off + ch].role = ROLE_DOWN;
+    byLane[off + ch].connLane = (uint8_t)ch;
+  }
+  items->swap(byLane);
+}
+
+// Work list in device memory: `items` in lane order, lane l running items
+// laneStart[l] .. laneStart[l + 1] - 1, and the collectives' pointer tables,
+// written to the pinned staging buffer and copied to the device in one copy
+// on the launch stream (after the previous launch, which may still read the
+// list).  The capacity must have been ensured.
+vcclResult_t stageWork(Clique* c, const StreamSet& ss, const std::vector<WorkItem>& items,
+                       const std::vector<uint32_t>& laneStart, const std::vector<Coll>& colls, LaunchDesc* d) {
+  const int k = c->stageNext;
+  c->stageNext ^= 1;
+  VCCL_HIPCHECK(hipEventSynchronize(c->stageEvent[k]));
+  char* stage = (char*)c->hStage[k];
+  const WorkLayout wl = workLayout(items.size());
+  memcpy(stage, items.data(), items.size() * sizeof(WorkItem));
+  memcpy(stage + wl.laneOff, laneStart.data(), laneStart.size() * sizeof(uint32_t));
+  CollArgs* sArgs = (CollArgs*)(stage + wl.argsOff);
+  for (size_t g = 0; g < colls.size(); ++g) sArgs[g] = colls[g].args;
+  hipStream_t ls = ss.list[ss.n - 1];
+  VCCL_HIPCHECK(hipStreamWaitEvent(ls, c->lastLaunchDone, 0));
+  VCCL_HIPCHECK(hipMemcpyAsync(c->dWork, stage, wl.argsOff + colls.size() * sizeof(CollArgs), hipMemcpyHostToDevice,
+                               ls));
+  VCCL_HIPCHECK(hipEventRecord(c->stageEvent[k], ls));
+  d->items = (const WorkItem*)c->dWork;
+  d->laneStart = (const uint32_t*)(c->dWork + wl.laneOff);
+  d->args = (const CollArgs*)(c->dWork + wl.argsOff);
+  d->stamps = c->dStamps;
+  return vcclSuccess;
+}
+
 }  // namespace
 
 vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
@@ -121,26 +168,32 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
 
   int nlanes = 0;
   size_t nitems = 0;
-  if (colls.size() == 1 && plans[0].nchannels <= MAX_INLINE) {
+  // a single collective whose lanes fit the descriptor runs from kernel
+  // arguments; a split tree takes 8 ceil(C / 8) + C lanes
+  const int singleLanes =
+      colls.size() == 1 ? (plans[0].split ? 8 * ((plans[0].nchannels + 7) / 8) : 0) + plans[0].nchannels : 0;
+  if (colls.size() == 1 && plans[0].split) {
+    // one item per lane: the work list takes the lanes as arranged
     std::vector<WorkItem> items;
     fillItems(c, colls[0], plans[0], 0, 0, &items);
-    if (plans[0].split) {
-      // channel ch: up half on lane ch, down half on lane off + ch (same XCD:
-      // off is a multiple of 8); lanes between the two groups stay idle
-      const int C = (int)items.size(), off = 8 * ((C + 7) / 8);
-      std::vector<WorkItem> byLane((size_t)(off + C));
-      for (int l = 0; l < off; ++l) {
-        byLane[l] = items[l < C ? l : 0];
-        byLane[l].role = l < C ? ROLE_UP : ROLE_IDLE;
-        byLane[l].connLane = (uint8_t)l;
-      }
-      for (int ch = 0; ch < C; ++ch) {
-        byLane[off + ch] = items[ch];
-        byLane[off + ch].role = ROLE_DOWN;
-        byLane[off + ch].connLane = (uint8_t)ch;
-      }
-      items.swap(byLane);
+    splitTreeLanes(&items);
+    if ((int)items.size() <= MAX_INLINE) {
+      d.items = nullptr;
+      d.inlineArgs = colls[0].args;
+      for (size_t i = 0; i < items.size(); ++i) d.inlineItems[i] = items[i];
+    } else {
+      r = cliqueEnsureWorkCapacity(c, items.size(), 1, (size_t)R);
+      if (r != vcclSuccess) return r;
+      std::vector<uint32_t> laneStart(items.size() + 1);
+      std::iota(laneStart.begin(), laneStart.end(), 0u);
+      r = stageWork(c, ss, items, laneStart, colls, &d);
+      if (r != vcclSuccess) return r;
     }
+    nlanes = (int)items.size();
+    nitems = items.size();
+  } else if (colls.size() == 1 && singleLanes <= MAX_INLINE) {
+    std::vector<WorkItem> items;
+    fillItems(c, colls[0], plans[0], 0, 0, &items);
     d.items = nullptr;
     d.inlineArgs = colls[0].args;
     for (size_t i = 0; i < items.size(); ++i) d.inlineItems[i] = items[i];
@@ -177,32 +230,16 @@ vcclResult_t launchColls(Clique* c, const std::vector<Coll>& collsIn) {
     for (size_t i = 0; i < items.size(); ++i) perLane[laneOf[i]].push_back((uint32_t)i);
     r = cliqueEnsureWorkCapacity(c, items.size(), colls.size(), colls.size() * (size_t)R);
     if (r != vcclSuccess) return r;
-    // stage: items (lane order), laneStart, args -> pinned buffer -> device
-    const int k = c->stageNext;
-    c->stageNext ^= 1;
-    VCCL_HIPCHECK(hipEventSynchronize(c->stageEvent[k]));
-    char* stage = (char*)c->hStage[k];
-    const WorkLayout wl = workLayout(items.size());
-    WorkItem* sItems = (WorkItem*)stage;
-    uint32_t* sLane = (uint32_t*)(stage + wl.laneOff);
-    CollArgs* sArgs = (CollArgs*)(stage + wl.argsOff);
-    uint32_t pos = 0;
+    std::vector<WorkItem> ordered;
+    ordered.reserve(items.size());
+    std::vector<uint32_t> laneStart((size_t)nlanes + 1);
     for (int l = 0; l < nlanes; ++l) {
-      sLane[l] = pos;
-      for (uint32_t i : perLane[l]) sItems[pos++] = items[i];
+      laneStart[l] = (uint32_t)ordered.size();
+      for (uint32_t i : perLane[l]) ordered.push_back(items[i]);
     }
-    sLane[nlanes] = pos;
-    for (size_t g = 0; g < colls.size(); ++g) sArgs[g] = colls[g].args;
-    hipStream_t ls = ss.list[ss.n - 1];
-    VCCL_HIPCHECK(hipStreamWaitEvent(ls, c->lastLaunchDone, 0));
-    // one copy of the whole list (items, lane starts, pointer tables)
-    VCCL_HIPCHECK(hipMemcpyAsync(c->dWork, stage, wl.argsOff + colls.size() * sizeof(CollArgs),
-                                 hipMemcpyHostToDevice, ls));
-    VCCL_HIPCHECK(hipEventRecord(c->stageEvent[k], ls));
-    d.items = (const WorkItem*)c->dWork;
-    d.laneStart = (const uint32_t*)(c->dWork + wl.laneOff);
-    d.args = (const CollArgs*)(c->dWork + wl.argsOff);
-    d.stamps = c->dStamps;
+    laneStart[nlanes] = (uint32_t)ordered.size();
+    r = stageWork(c, ss, ordered, laneStart, colls, &d);
+    if (r != vcclSuccess) return r;
     nitems = items.size();
   }
   d.nlanes = (uint32_t)nlanes;

@@ -162,10 +162,15 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   int nch = (int)pickPos(c->apiTune.nchannels, c->envTune.nchannels, dfltC);
   nch = std::max(1, std::min(nch, c->maxLanes));
   // --- a Simple tree launched alone runs each channel as two concurrent
-  // halves (reduce-up and broadcast-down) on two lanes of one XCD; the pair
-  // of lanes fits the inline launch with up to 16 channels
+  // halves (reduce-up and broadcast-down) on two lanes of one XCD: channel
+  // ch's up half on lane ch, its down half on lane 8 ceil(C / 8) + ch, so C
+  // channels take 8 ceil(C / 8) + C of the set's lanes
   bool split = single && c->treeSplit && c->xcdMap && algo == ALGO_TREE && proto == PROTO_SIMPLE;
-  if (split) nch = std::min(nch, 16);
+  if (split) {
+    int cap = 1;
+    while (cap < 32 && 8 * (int)ceilDiv(cap + 1, 8) + cap + 1 <= c->maxLanes) ++cap;
+    nch = std::min(nch, cap);
+  }
   // --- workgroup size
   long dfltT = (S >= (256u << 10)) ? 512 : 256;
   // LL128 receives are bound by the lines in flight: from 16 MiB, 1024

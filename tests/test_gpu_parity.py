@@ -226,6 +226,43 @@ def test_tree_halves_and_fused_channels(vccl, comms_for, split):
             os.environ["VCCL_TREE_SPLIT"] = old
 
 
+def test_wide_split_tree_runs_from_the_work_list(vccl):
+    """With the lane limit raised to 64 (VCCL_MAX_CHANNELS), a split tree of
+    more than 16 channels takes more lanes (8 ceil(C / 8) + C) than the launch
+    descriptor holds and runs from the device work list: 24 and 32 channels
+    at 8 and 16 ranks, every rank against the oracle's tree fold."""
+    import os
+    old = os.environ.get("VCCL_MAX_CHANNELS")
+    os.environ["VCCL_MAX_CHANNELS"] = "64"
+    try:
+        for R in (8, 16):
+            comms = vccl.vcclCommInitAll(R)
+            try:
+                for dtype, op, n, C, chunk in (("bfloat16", "sum", 300007, 32, 4096),
+                                               ("float32", "sum", 200003, 24, 4096),
+                                               ("int32", "max", 150001, 32, 2048)):
+                    print(f"wide split tree R={R} {dtype} {op} C={C}", flush=True)
+                    xs = _inputs(R, dtype, n, wl=3, extra=R * 7 + C)
+                    H.tune(vccl, comms, "tree", "simple", nchannels=C, chunk=chunk)
+                    try:
+                        got = _run(vccl, comms, "allreduce", xs, n, dtype, op)
+                        info = vccl.vcclCommGetLastPlan(comms[0])
+                    finally:
+                        H.untune(vccl, comms)
+                    assert info["nchannels"] == C and info["nlanes"] == 8 * ((C + 7) // 8) + C, (R, C, info)
+                    want = folds.tree_allreduce(xs, op, dtype, C)
+                    for r in range(R):
+                        _assert_bits(got[r], want, f"wide split tree {dtype} {op} R={R} C={C} rank {r}")
+            finally:
+                for c in comms:
+                    vccl.vcclCommDestroy(c)
+    finally:
+        if old is None:
+            del os.environ["VCCL_MAX_CHANNELS"]
+        else:
+            os.environ["VCCL_MAX_CHANNELS"] = old
+
+
 @pytest.mark.parametrize("R,P", [(4, 2), (8, 2), (8, 4), (16, 4), (16, 8), (12, 3)])
 def test_chain_tree_topology(vccl, R, P):
     """VCCL_TREE_RANKS_PER_NODE=P: chains within groups of P ranks, the double
