@@ -167,9 +167,10 @@ vcclResult_t planColl(Clique* c, const Coll& coll, Plan* plan, bool single) {
   // channels take 8 ceil(C / 8) + C of the set's lanes
   bool split = single && c->treeSplit && c->xcdMap && algo == ALGO_TREE && proto == PROTO_SIMPLE;
   if (split) {
-    int cap = 1;
+    int cap = 0;
     while (cap < 32 && 8 * (int)ceilDiv(cap + 1, 8) + cap + 1 <= c->maxLanes) ++cap;
-    nch = std::min(nch, cap);
+    if (cap == 0) split = false;  // not even one channel's pair of lanes fits
+    else nch = std::min(nch, cap);
   }
   // --- workgroup size
   long dfltT = (S >= (256u << 10)) ? 512 : 256;

@@ -82,3 +82,19 @@ def test_rejects_bad_arguments(vccl):
         assert e.value.code == vccl.vcclInvalidArgument
     with pytest.raises(vccl.VcclError):
         vccl.vcclDebugPlanHost(8, 0, 8, vccl.vcclFloat32, tuning=dict(nthreads=100))
+
+
+def test_split_tree_fits_the_lane_limit(vccl):
+    """A Simple tree launched alone runs as split halves on 8 ceil(C / 8) + C
+    lanes, within the set's lane limit: 16 ranks (32 lanes) keep at most 16
+    split channels, 8 ranks (64 lanes) up to 32; inside a group the channels
+    stay fused, one lane each."""
+    n = (64 << 20) // 2
+    for R, asked, channels in ((16, 24, 16), (16, 16, 16), (8, 32, 32), (8, 24, 24), (8, 20, 20)):
+        tune = dict(algo=vccl.vcclAlgoTree, proto=vccl.vcclProtoSimple, nchannels=asked)
+        p = vccl.vcclDebugPlanHost(R, 0, n, vccl.vcclBfloat16, single=1, tuning=tune)
+        assert p["algo"] == vccl.vcclAlgoTree and p["nchannels"] == channels, (R, asked, p)
+        assert p["nlanes"] == 8 * ((channels + 7) // 8) + channels, (R, asked, p)
+        assert p["nlanes"] <= max(32, min(64, (2 * 256 // R) // 8 * 8))
+        g = vccl.vcclDebugPlanHost(R, 0, n, vccl.vcclBfloat16, single=0, tuning=tune)
+        assert g["nlanes"] == g["nchannels"] == asked, (R, asked, g)
